@@ -1,0 +1,207 @@
+"""Seeded synthetic inputs shaped like the paper's lattice Boltzmann workloads.
+
+This module holds geometry and initial-condition generators only: solid
+masks, analytic diffuse-solid fields, liquid drops and slabs, the interfacial
+parameters of a target contact angle, and seeded random population states for
+parity checks.  It holds none of the step's arithmetic and is shared by the
+tests, the benchmark and the oracle-side checks.
+
+Arrays are returned with shape (nx, ny) or (nx, ny, nz) and must be flattened
+in Fortran order (x fastest) to match the libraries' node order
+n = x + nx*(y + ny*z); :func:`flat` does that.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def flat(a: np.ndarray) -> np.ndarray:
+    """Flatten an (nx, ny[, nz]) array to node order n = x + nx*(y + ny*z)."""
+    return np.ascontiguousarray(np.asarray(a).reshape(-1, order="F"))
+
+
+def unflat(v: np.ndarray, shape) -> np.ndarray:
+    """Inverse of :func:`flat`."""
+    return np.asarray(v).reshape(shape, order="F")
+
+
+# ---------------------------------------------------------------------------
+# interfacial parameters
+
+def kappas_from_tensions(g12: float, g13: float, g23: float, alpha: float = 1.0):
+    """kappa_1..3 from the three pairwise tensions (Sec. II.A: inversion of
+    gamma_nm = alpha (kappa_n + kappa_m) / 6)."""
+    k1 = 3.0 / alpha * (g12 + g13 - g23)
+    k2 = 3.0 / alpha * (g12 - g13 + g23)
+    k3 = 3.0 / alpha * (-g12 + g13 + g23)
+    return (k1, k2, k3)
+
+
+def kappas_for_angle(theta_deg: float, gamma: float = 2.5e-3, alpha: float = 1.0):
+    """kappa_1..3 for a target equilibrium angle, with the liquid-gas and
+    solid-liquid tensions both fixed at ``gamma`` and the solid-gas tension
+    set by Young's law (the convention of Supp. D)."""
+    g12 = g23 = gamma
+    g13 = g12 + g23 * math.cos(math.radians(theta_deg))
+    return kappas_from_tensions(g12, g13, g23, alpha)
+
+
+# ---------------------------------------------------------------------------
+# geometry helpers
+
+def tanh_profile(d: np.ndarray, alpha: float = 1.0) -> np.ndarray:
+    """1/2 + 1/2 tanh(d / (2 alpha)) of a signed distance d (positive inside)."""
+    return 0.5 + 0.5 * np.tanh(np.asarray(d, dtype=np.float64) / (2.0 * alpha))
+
+
+def _coords(shape):
+    return np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
+
+
+def periodic_slab_distance(coord: np.ndarray, lo: float, hi: float, period: int) -> np.ndarray:
+    """Signed distance (positive inside) to the periodic slab lo <= s <= hi."""
+    mid = 0.5 * (lo + hi)
+    half = 0.5 * (hi - lo)
+    r = np.abs(((coord - mid + 0.5 * period) % period) - 0.5 * period)
+    return half - r
+
+
+def min_image(d: np.ndarray, period: int) -> np.ndarray:
+    return (d + 0.5 * period) % period - 0.5 * period
+
+
+def drop_field(shape, center, radius, C1=None, alpha: float = 1.0,
+               open_axis: int | None = None) -> np.ndarray:
+    """Liquid drop: tanh-smoothed disc / ball of ``radius`` at ``center``,
+    cut to the fluid side by (1 - C1).  Distances use the minimum image
+    except along ``open_axis`` (the wall normal of a sessile drop), where the
+    plain difference is used so that the drop does not wrap through the wall
+    into the far side of the box."""
+    X = _coords(shape)
+    r2 = np.zeros(shape)
+    for d, (xd, c) in enumerate(zip(X, center)):
+        dd = xd - c if d == open_axis else min_image(xd - c, shape[d])
+        r2 += dd ** 2
+    C2 = tanh_profile(radius - np.sqrt(r2), alpha)
+    if C1 is not None:
+        C2 = C2 * (1.0 - C1)
+    return C2
+
+
+@dataclass
+class Workload:
+    """One lattice problem: geometry, parameters and initial liquid."""
+    name: str
+    dim: int
+    shape: tuple
+    kappa: tuple
+    alpha: float = 1.0
+    tau: float = 1.0
+    mobility: float = 0.1
+    gravity: tuple = (0.0, 0.0, 0.0)
+    mask: np.ndarray | None = None      # solid region S (uint8)
+    C1: np.ndarray | None = None        # diffuse solid (analytic), or None -> solid stage
+    C2: np.ndarray | None = None        # initial liquid
+    wall_level: float | None = None     # C1 = 1/2 plane of a flat wall (for angle fits)
+    wall_axis: int = 1
+    solid_stage: dict = field(default_factory=dict)
+    seed: int = 0
+
+    @property
+    def nodes(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def flat_wall(dim: int, shape, thickness: int, alpha: float = 1.0):
+    """Solid slab occupying the first ``thickness`` layers along the last
+    axis; its C1 is the analytic tanh of the periodic signed distance, with
+    the faces half-way between nodes."""
+    axis = dim - 1
+    X = _coords(shape)
+    lo, hi = -0.5, thickness - 0.5
+    d = periodic_slab_distance(X[axis], lo, hi, shape[axis])
+    mask = (d > 0).astype(np.uint8)
+    return mask, tanh_profile(d, alpha), hi
+
+
+def sessile_drop(dim: int, shape, thickness: int, radius: float, theta_deg: float,
+                 seed: int = 0, noise: float = 0.0, alpha: float = 1.0,
+                 tau: float = 1.0, mobility: float = 0.1, name: str = "sessile") -> Workload:
+    """Drop (semicircle / hemisphere) centred on a flat diffuse wall."""
+    mask, C1, face = flat_wall(dim, shape, thickness, alpha)
+    center = [0.5 * n for n in shape]
+    center[dim - 1] = face
+    C2 = drop_field(shape, center, radius, C1, alpha, open_axis=dim - 1)
+    if noise > 0.0:
+        rng = np.random.default_rng(seed)
+        C2 = C2 + noise * rng.uniform(-1.0, 1.0, size=shape) * (C1 < 0.5)
+    return Workload(name=name, dim=dim, shape=tuple(shape), kappa=kappas_for_angle(theta_deg),
+                    alpha=alpha, tau=tau, mobility=mobility, mask=mask, C1=C1, C2=C2,
+                    wall_level=face, wall_axis=dim - 1, seed=seed)
+
+
+def config_2d_contact_angle(theta_deg: float, seed: int = 1, noise: float = 0.0) -> Workload:
+    """D2Q9 128x64 periodic, 8-node bottom wall, semicircular drop R = 25."""
+    return sessile_drop(2, (128, 64), 8, 25.0, theta_deg, seed=seed, noise=noise,
+                        name=f"d2q9-128x64-wall8-R25-theta{theta_deg:g}")
+
+
+def config_3d_sessile(theta_deg: float, n: int = 128, seed: int = 2, noise: float = 0.0,
+                      radius: float = 30.0, thickness: int = 6) -> Workload:
+    """D3Q19 n^3 periodic, 6-node bottom slab, hemispherical drop R = 30."""
+    return sessile_drop(3, (n, n, n), thickness, radius, theta_deg, seed=seed, noise=noise,
+                        name=f"d3q19-{n}^3-slab{thickness}-R{radius:g}-theta{theta_deg:g}")
+
+
+def pillar_mask(shape, base: int = 8, width: int = 8, pitch: int = 16, height: int = 32,
+                jitter: int = 2, seed: int = 3) -> np.ndarray:
+    """Square micropillars on a base slab (z < base), pillars of ``width``
+    on a ``pitch`` lattice, each offset by a seeded integer jitter."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    mask = np.zeros(shape, dtype=np.uint8)
+    mask[:, :, :base] = 1
+    for px in range(nx // pitch):
+        for py in range(ny // pitch):
+            jx, jy = rng.integers(-jitter, jitter + 1, size=2)
+            x0 = px * pitch + (pitch - width) // 2 + int(jx)
+            y0 = py * pitch + (pitch - width) // 2 + int(jy)
+            xs = np.arange(x0, x0 + width) % nx
+            ys = np.arange(y0, y0 + width) % ny
+            mask[np.ix_(xs, ys, np.arange(base, base + height))] = 1
+    return mask
+
+
+def config_3d_pillars(shape=(256, 256, 192), theta_deg: float = 120.0, seed: int = 3,
+                      liquid=(44, 104)) -> Workload:
+    """Micropillar array with a liquid slab above it; C1 comes from the solid
+    stage (5000 steps, beta = 1e-3, Omega = 2e-4)."""
+    mask = pillar_mask(shape, seed=seed)
+    X = _coords(shape)
+    C2 = tanh_profile(periodic_slab_distance(X[2], liquid[0], liquid[1], shape[2]))
+    return Workload(name=f"d3q19-{shape[0]}x{shape[1]}x{shape[2]}-pillars", dim=3,
+                    shape=tuple(shape), kappa=kappas_for_angle(theta_deg), mask=mask, C1=None,
+                    C2=C2, gravity=(0.0, 0.0, -1e-5),
+                    solid_stage=dict(n_steps=5000, beta=1e-3, omega=2e-4), seed=seed)
+
+
+def sinusoid_mask(shape, amplitude: float, wavelength: float, base: float) -> np.ndarray:
+    """2D solid below y_s(x) = base + A sin(2 pi x / lambda)."""
+    X, Y = _coords(shape)
+    ys = base + amplitude * np.sin(2.0 * np.pi * X / wavelength)
+    return (Y <= ys).astype(np.uint8)
+
+
+def random_postcollision_state(Q: int, shape, C2: np.ndarray, seed: int, amp: float = 1e-3):
+    """Seeded random post-collision populations around a liquid field:
+    f* = amp * U(-1, 1); g*_0 = C2 + amp * U(-1, 1); g*_i = amp * U(-1, 1)
+    for i > 0 (index 0 is the rest direction in both libraries)."""
+    rng = np.random.default_rng(seed)
+    N = int(np.prod(shape))
+    fs = amp * rng.uniform(-1.0, 1.0, size=(Q, N))
+    gs = amp * rng.uniform(-1.0, 1.0, size=(Q, N))
+    gs[0] += flat(C2)
+    return fs, gs
