@@ -1,0 +1,193 @@
+/*
+ * dsm.h -- C ABI of libdsm.so, the MI355X (gfx950) implementation of the
+ * diffuse-solid ternary free-energy lattice Boltzmann step of
+ * Oktasendra, Rennick, Avis, Panter and Kusumaatmaja, "The Diffuse Solid
+ * Method for Wetting and Multiphase Fluid Simulations in Complex
+ * Geometries" (arXiv 2504.19941), Sec. II.B.
+ *
+ * Components: 1 = diffuse solid (C1), 2 = liquid (C2), 3 = gas
+ * (C3 = 1 - C1 - C2, Sec. II.A).  dim 2 runs D2Q9 (velocity set and weights
+ * of Sec. II.B), dim 3 runs D3Q19; every axis is periodic.
+ *
+ * Layout.  Host fields are arrays of N = nx*ny*nz doubles in node order
+ * n = x + nx*(y + ny*z) (x fastest; nz = 1 in 2D).  Vector fields (u) are
+ * dim consecutive planes of N.  Population arrays are Q planes of N
+ * ([Q][N], direction-major) in the direction order: rest, then each velocity
+ * followed by its opposite -- D2Q9: (0,0) (1,0) (-1,0) (0,1) (0,-1) (1,1)
+ * (-1,-1) (1,-1) (-1,1); D3Q19: (0,0,0) +-x +-y +-z (1,1,0) (-1,-1,0)
+ * (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1)
+ * (0,1,-1) (0,-1,1).
+ *
+ * Ownership.  The caller allocates ONE device buffer of dsm_required_bytes()
+ * bytes (e.g. a torch uint8 CUDA tensor) and keeps it alive until
+ * dsm_destroy(); the library carves every device array out of it and never
+ * allocates device memory.  The library owns only the small host handle.
+ * Host arrays passed in or out belong to the caller; any output pointer may
+ * be NULL to skip that field.
+ *
+ * Ordering.  Every call enqueues its device work on the HIP stream given to
+ * dsm_create().  dsm_step() returns without synchronising except when it
+ * reaches a stability check (every reduce_every steps).  Calls that return
+ * host data synchronise the stream.  A handle must not be used from two
+ * threads at once.
+ *
+ * Errors.  Calls return DSM_OK (0) or a negative DSM_E* code; the message of
+ * the last failure on the calling thread is returned by dsm_last_error().
+ * Arguments are validated before any device work is issued, so invalid
+ * arguments never touch the GPU.
+ *
+ * Arithmetic is FP32 on the device, with FP64 for the global reductions
+ * (masses, free energy, kinetic energy).
+ */
+#ifndef DSM_H
+#define DSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DSM_OK = 0,
+    DSM_EINVAL = -1,    /* invalid argument                                   */
+    DSM_ENOMEM = -2,    /* device buffer smaller than dsm_required_bytes()    */
+    DSM_EDEVICE = -3,   /* a HIP call failed                                  */
+    DSM_EUNSTABLE = -4, /* non-finite values found by the stability check     */
+    DSM_ESTATE = -5     /* call out of order (e.g. dsm_step before a liquid)  */
+};
+
+/* flags of dsm_init_solid */
+enum { DSM_SOLID_RESET = 1, DSM_SOLID_REMASK = 2 };
+
+/* step implementations: the single fused kernel, or three kernels
+ * (moment, chemical potential, collide-stream) kept as a cross-check */
+enum { DSM_KERNEL_FUSED = 0, DSM_KERNEL_SPLIT = 1 };
+
+typedef struct {
+    int dim;             /* 2 (D2Q9, nz must be 1) or 3 (D3Q19)                  */
+    int nx, ny, nz;      /* lattice size, each >= 4 (nz = 1 in 2D)               */
+    double kappa[3];     /* kappa_1 solid, kappa_2 liquid, kappa_3 gas (>= 0,
+                            kappa_2 + kappa_3 > 0); Sec. II.A bulk and gradient
+                            energies with kappa'_n = alpha^2 kappa_n              */
+    double alpha;        /* interface width (> 0); the paper uses 1               */
+    double tau;          /* hydrodynamic relaxation time (> 1/2); rho = 1 and a
+                            single tau for both fluids                          */
+    double mobility;     /* Cahn-Hilliard mobility M (> 0): tau_g = 1/2 + 3 M    */
+    double gravity[3];   /* body-force density on the liquid, F_g = C2 g          */
+    int reduce_every;    /* K > 0: dsm_step checks for non-finite values every
+                            K steps (synchronising); 0 disables the check        */
+    int kernel;          /* DSM_KERNEL_FUSED (default) or DSM_KERNEL_SPLIT        */
+} dsm_params;
+
+typedef struct dsm_sim dsm_sim;
+
+/* Bytes of device memory a simulation with these parameters needs; 0 if the
+ * parameters are invalid.  Pure host function. */
+size_t dsm_required_bytes(const dsm_params* p);
+
+/* Problem statement of Sec. II: lattice, solid region S (Sec. II.A, the
+ * region the confining potential holds the solid to), kappa_m and alpha
+ * (Sec. II.A), tau and M (Sec. II.B), body force.
+ *   mask      host, N bytes, 1 where the node lies in S (may be NULL: S empty).
+ *             The solid starts as the sharp indicator C1 = 1[S].
+ *   dev_buf   device pointer to dev_bytes >= dsm_required_bytes(p) bytes,
+ *             256-byte aligned, owned by the caller.
+ *   stream    hipStream_t (NULL = default stream) for all device work.
+ *   out       receives the handle.
+ * Errors: DSM_EINVAL (bad parameter or pointer), DSM_ENOMEM (dev_bytes too
+ * small), DSM_EDEVICE. */
+int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t dev_bytes,
+               void* stream, dsm_sim** out);
+
+/* Solid stage (Sec. II.B): n_steps lattice Boltzmann steps of the
+ * solid-relaxation functional with confining strength beta and range
+ * penalty Omega, relaxation times tau_s and tau_g = 1/2 + 3 mobility_s, every
+ * node fluid, no body force.  flags: DSM_SOLID_RESET restarts from
+ * C1 = 1[S] (otherwise the solid stage continues from its live state, so a
+ * schedule can change beta and Omega between calls); DSM_SOLID_REMASK
+ * replaces S by {C1 > 1/2} after the run (the two-step initialisation for
+ * sharp corners).  On return C1 is frozen to the relaxed field; a liquid must
+ * then be set with dsm_set_liquid.  Errors: DSM_EINVAL, DSM_EDEVICE. */
+int dsm_init_solid(dsm_sim* s, int n_steps, double beta, double omega, double tau_s,
+                   double mobility_s, int flags);
+
+/* Alternative to the solid stage: a given diffuse solid C1 (host, N values;
+ * stored in FP32).  Invalidates any liquid state.  Errors: DSM_EINVAL,
+ * DSM_EDEVICE. */
+int dsm_set_solid_field(dsm_sim* s, const double* C1);
+
+/* Liquid initial condition at t = 0 (host, N values): f = 0 and
+ * g = g_eq(C2, mu(C2), u = 0) at every node.  Errors: DSM_EINVAL,
+ * DSM_EDEVICE. */
+int dsm_set_liquid(dsm_sim* s, const double* C2);
+
+/* Replaces the body-force density (between steps, e.g. for ramps). */
+int dsm_set_gravity(dsm_sim* s, const double g[3]);
+
+/* n fluid-stage time steps (Sec. II.B, frozen solid), stream-ordered.
+ * Errors: DSM_EINVAL (n < 0), DSM_ESTATE (no liquid set), DSM_EUNSTABLE
+ * (stability check failed; the state is left as computed), DSM_EDEVICE. */
+int dsm_step(dsm_sim* s, int n);
+
+/* Discrete free energy of the current state (FP64 reduction; synchronises):
+ * fluid stage, the frozen-solid functional of Sec. II.B without its constant
+ * C1 terms; solid stage, the solid-relaxation functional.  Square gradients
+ * are lattice link sums whose node derivative equals the step's chemical
+ * potential.  E_kin = sum over fluid nodes of rho |u|^2 / 2.  Either pointer
+ * may be NULL.  Errors: DSM_ESTATE, DSM_EDEVICE. */
+int dsm_free_energy(dsm_sim* s, double* F, double* E_kin);
+
+/* Total amounts sum_x C1, C2, C3 (FP64 reduction; synchronises). */
+int dsm_mass(dsm_sim* s, double m[3]);
+
+/* Macroscopic fields of the current state (synchronises): C1, C2, C3, the
+ * velocity u (dim planes) and the pressure P = p~ / 3, where p~ is the zeroth
+ * moment of f.  Any pointer may be NULL.  Errors: DSM_ESTATE, DSM_EDEVICE. */
+int dsm_fields(dsm_sim* s, double* C1, double* C2, double* C3, double* u, double* p);
+
+/* Chemical potential mu of the current state (host, N values). */
+int dsm_chemical_potential(dsm_sim* s, double* mu);
+
+/* Post-stream populations of the current state as FP64 [Q][N] arrays, and
+ * the inverse (the given arrays become the state at the current time).
+ * Errors: DSM_ESTATE, DSM_EDEVICE. */
+int dsm_get_populations(dsm_sim* s, double* f, double* g);
+int dsm_set_populations(dsm_sim* s, const double* f, const double* g);
+
+/* Sets the state to the streaming of the given post-collision populations
+ * (FP64 [Q][N]); the next step starts by streaming them, with bounce-back. */
+int dsm_set_postcollision(dsm_sim* s, const double* fs, const double* gs);
+
+/* Checkpoint: an opaque byte image of the live state (populations, C1, S,
+ * body force, step counter).  dsm_set_state on a handle created with the same
+ * parameters continues bit-for-bit.  Errors: DSM_EINVAL (size mismatch),
+ * DSM_ESTATE, DSM_EDEVICE. */
+size_t dsm_state_bytes(const dsm_sim* s);
+int dsm_get_state(dsm_sim* s, void* host, size_t bytes);
+int dsm_set_state(dsm_sim* s, const void* host, size_t bytes);
+
+/* Steps taken in the fluid stage since the last dsm_set_liquid. */
+long long dsm_step_count(const dsm_sim* s);
+
+/* Launch shape of the fused step kernel: the workgroup tile (variant in
+ * [0, dsm_tiling_variants(dim)); 3D: 0 = 32x8, 1 = 64x4, 2 = 64x8, 3 = 32x16
+ * columns; 2D: 0 = 128, 1 = 256, 2 = 64 columns) and the number of planes
+ * (1..4096) each workgroup marches through along the slowest axis.  Results
+ * do not depend on it beyond round-off-free reordering of independent nodes:
+ * every choice computes bit-identical populations.  Defaults: variant 0,
+ * 16 planes.  Errors: DSM_EINVAL. */
+int dsm_set_tiling(dsm_sim* s, int variant, int planes);
+int dsm_tiling_variants(int dim);
+
+/* Releases the host handle (the device buffer stays the caller's). */
+int dsm_destroy(dsm_sim* s);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* dsm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

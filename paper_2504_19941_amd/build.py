@@ -1,0 +1,40 @@
+"""Builds libdsm.so, the gfx950 HIP library behind include/dsm.h, in-tree.
+
+    python -m paper_2504_19941_amd.build        # or: python paper_2504_19941_amd/build.py
+"""
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libdsm.so")
+SOURCES = ["dsm_api.hip", "dsm_kernels.hip", "dsm_fused.hip"]
+ARCH = "gfx950"
+
+
+def hipcc_command(out: str = LIB, extra=()):
+    return [
+        "hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        # packed FP32 instructions are kept out of the generated code
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-Wall", "-I", os.path.join(ROOT, "include"),
+        *extra,
+        "-o", out, *[os.path.join(CSRC, s) for s in SOURCES],
+    ]
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    cmd = hipcc_command(extra=extra)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    tmp = LIB + ".tmp"
+    cmd[cmd.index("-o") + 1] = tmp
+    subprocess.run(cmd, check=True, cwd=PKG)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,581 @@
+// dsm_api.hip -- host side of the libdsm.so C ABI (include/dsm.h).
+//
+// Validates arguments before any HIP call, carves the device arrays out of
+// the caller's buffer, converts host FP64 fields to device FP32 and back, and
+// enqueues the kernels on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dsm.h"
+#include "dsm_internal.h"
+
+using namespace dsm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(DSM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr uint32_t kStateMagic = 0x44534d31u;  // "DSM1"
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int lattice_q(int dim) { return dim == 2 ? 9 : 19; }
+
+// Returns an error message for invalid parameters, or nullptr.
+const char* validate(const dsm_params* p) {
+    if (!p) return "params is NULL";
+    if (p->dim != 2 && p->dim != 3) return "dim must be 2 or 3";
+    if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
+    if (p->dim == 2 && p->nz != 1) return "nz must be 1 when dim == 2";
+    if (p->dim == 3 && p->nz < 4) return "nz must be >= 4 when dim == 3";
+    const double nodes = (double)p->nx * (double)p->ny * (double)p->nz;
+    if (nodes > 2147483647.0) return "lattice has more than 2^31 - 1 nodes";
+    for (int k = 0; k < 3; ++k)
+        if (!(p->kappa[k] >= 0.0) || !isfinite(p->kappa[k])) return "kappa must be finite and >= 0";
+    if (!(p->kappa[1] + p->kappa[2] > 0.0)) return "kappa_2 + kappa_3 must be > 0";
+    if (!(p->alpha > 0.0) || !isfinite(p->alpha)) return "alpha must be > 0";
+    if (!(p->tau > 0.5) || !isfinite(p->tau)) return "tau must be > 1/2";
+    if (!(p->mobility > 0.0) || !isfinite(p->mobility)) return "mobility must be > 0";
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(p->gravity[k])) return "gravity must be finite";
+    if (p->dim == 2 && p->gravity[2] != 0.0) return "gravity[2] must be 0 when dim == 2";
+    if (p->reduce_every < 0) return "reduce_every must be >= 0";
+    if (p->kernel != DSM_KERNEL_FUSED && p->kernel != DSM_KERNEL_SPLIT) return "unknown kernel";
+    return nullptr;
+}
+
+struct Layout {
+    size_t off_f[2], off_g[2], off_c1, off_mask, off_phi, off_mu, off_aux, off_part, off_red, off_flag;
+    size_t total;
+};
+
+Layout make_layout(const dsm_params* p) {
+    Layout L;
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    const size_t Q = (size_t)lattice_q(p->dim);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.off_f[0] = take(Q * N * sizeof(float));
+    L.off_g[0] = take(Q * N * sizeof(float));
+    L.off_f[1] = take(Q * N * sizeof(float));
+    L.off_g[1] = take(Q * N * sizeof(float));
+    L.off_c1 = take(N * sizeof(float));
+    L.off_mask = take(N);
+    L.off_phi = take(N * sizeof(float));
+    L.off_mu = take(N * sizeof(float));
+    L.off_aux = take(4 * N * sizeof(float));
+    L.off_part = take((size_t)kReduceBlocks * RED_SLOTS * sizeof(double));
+    L.off_red = take(RED_SLOTS * sizeof(double));
+    L.off_flag = take(4 * sizeof(int));
+    L.total = o;
+    return L;
+}
+
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t dim, nx, ny, nz, stage, pull;
+    int64_t steps;
+    double gravity[3];
+    double beta, omega, tau_s, taug_s;
+};
+
+}  // namespace
+
+struct dsm_sim {
+    dsm_params p;
+    int Q;
+    long long N;
+    Geom geom;
+    hipStream_t stream;
+    DevArrays d;
+    int cur;       // buffer pair holding the live state
+    int pull;      // 1: live buffers hold post-collision populations
+    int stage;     // 0: no live state, 1: solid stage live, 2: fluid stage live
+    long long steps;
+    double beta, omega, tau_s, taug_s;
+    int tile_variant;  // workgroup tile of the fused step
+    int tile_planes;   // planes marched per workgroup
+    std::vector<float> stage_buf;  // host staging for conversions
+};
+
+namespace {
+
+Phys make_phys(const dsm_sim* s, int stage) {
+    Phys ph;
+    ph.k1 = (float)s->p.kappa[0];
+    ph.k2 = (float)s->p.kappa[1];
+    ph.k3 = (float)s->p.kappa[2];
+    ph.a2 = (float)(s->p.alpha * s->p.alpha);
+    ph.alpha = (float)s->p.alpha;
+    double tau = stage == 1 ? s->tau_s : s->p.tau;
+    double taug = stage == 1 ? s->taug_s : 0.5 + 3.0 * s->p.mobility;
+    ph.inv_tau = (float)(1.0 / tau);
+    ph.inv_taug = (float)(1.0 / taug);
+    ph.fpref = (float)(1.0 - 0.5 / tau);
+    // user axes -> stored axes (2D stores y along the slow axis)
+    if (s->p.dim == 2) {
+        ph.grav[0] = (float)s->p.gravity[0];
+        ph.grav[1] = 0.f;
+        ph.grav[2] = (float)s->p.gravity[1];
+    } else {
+        for (int k = 0; k < 3; ++k) ph.grav[k] = (float)s->p.gravity[k];
+    }
+    ph.beta = (float)s->beta;
+    ph.omega = (float)s->omega;
+    ph.stage = stage;
+    return ph;
+}
+
+int upload_field(dsm_sim* s, const double* host, float* dev) {
+    const size_t N = (size_t)s->N;
+    s->stage_buf.resize(N);
+    for (size_t n = 0; n < N; ++n) s->stage_buf[n] = (float)host[n];
+    HIP_TRY(hipMemcpyAsync(dev, s->stage_buf.data(), N * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return DSM_OK;
+}
+
+int download_field(dsm_sim* s, const float* dev, double* host, size_t count) {
+    s->stage_buf.resize(count);
+    HIP_TRY(hipMemcpyAsync(s->stage_buf.data(), dev, count * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t n = 0; n < count; ++n) host[n] = (double)s->stage_buf[n];
+    return DSM_OK;
+}
+
+// Observables of the live state into phi, mu and aux.
+int observe(dsm_sim* s) {
+    const Phys ph = make_phys(s, s->stage);
+    const int c = s->cur;
+    HIP_TRY(launch_moment(s->p.dim, s->geom, s->d.g[c], s->d.phi, s->pull, s->stream));
+    HIP_TRY(launch_mu(s->p.dim, s->geom, ph, s->d.phi, s->d.c1, s->d.mask, s->d.mu, s->stream));
+    HIP_TRY(launch_observe(s->p.dim, s->geom, ph, s->d.f[c], s->d.c1, s->d.phi, s->d.mu, s->pull, s->d.aux,
+                           s->stream));
+    return DSM_OK;
+}
+
+int reduce(dsm_sim* s, double out[RED_SLOTS]) {
+    int rc = observe(s);
+    if (rc) return rc;
+    const Phys ph = make_phys(s, s->stage);
+    HIP_TRY(launch_reduce(s->p.dim, s->geom, ph, s->d.c1, s->d.phi, s->d.mask, s->d.aux, s->d.partials,
+                          s->d.red, s->stream));
+    HIP_TRY(hipMemcpyAsync(out, s->d.red, RED_SLOTS * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return DSM_OK;
+}
+
+// One time step of the live stage: reads buffer pair cur, writes 1 - cur.
+int one_step(dsm_sim* s) {
+    const Phys ph = make_phys(s, s->stage);
+    const int c = s->cur, n = 1 - s->cur;
+    if (s->p.kernel == DSM_KERNEL_FUSED) {
+        HIP_TRY(launch_step_fused(s->p.dim, s->geom, ph, s->d.f[c], s->d.g[c], s->d.f[n], s->d.g[n], s->d.c1,
+                                  s->d.mask, s->pull, s->d.flag, s->tile_variant, s->tile_planes, s->stream));
+    } else {
+        HIP_TRY(launch_moment(s->p.dim, s->geom, s->d.g[c], s->d.phi, s->pull, s->stream));
+        HIP_TRY(launch_mu(s->p.dim, s->geom, ph, s->d.phi, s->d.c1, s->d.mask, s->d.mu, s->stream));
+        HIP_TRY(launch_collide_split(s->p.dim, s->geom, ph, s->d.f[c], s->d.g[c], s->d.f[n], s->d.g[n],
+                                     s->d.c1, s->d.phi, s->d.mu, s->pull, s->d.flag, s->stream));
+    }
+    s->cur = n;
+    s->pull = 1;
+    return DSM_OK;
+}
+
+// Sets f = 0, g = g_eq(phi, mu(phi), 0) from the field already in d.phi.
+int init_populations(dsm_sim* s, int stage) {
+    const Phys ph = make_phys(s, stage);
+    HIP_TRY(launch_mu(s->p.dim, s->geom, ph, s->d.phi, s->d.c1, s->d.mask, s->d.mu, s->stream));
+    HIP_TRY(launch_init_populations(s->p.dim, s->geom, s->d.phi, s->d.mu, s->d.f[0], s->d.g[0], s->stream));
+    s->cur = 0;
+    s->pull = 0;
+    return DSM_OK;
+}
+
+int check_flag(dsm_sim* s) {
+    int h[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(h, s->d.flag, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (h[0]) return fail(DSM_EUNSTABLE, "non-finite values in the lattice state");
+    return DSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dsm_required_bytes(const dsm_params* p) {
+    if (validate(p)) return 0;
+    return make_layout(p).total;
+}
+
+int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t dev_bytes, void* stream,
+               dsm_sim** out) {
+    if (!out) return fail(DSM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (const char* msg = validate(p)) return fail(DSM_EINVAL, msg);
+    if (!dev_buf) return fail(DSM_EINVAL, "dev_buf is NULL");
+    if (((uintptr_t)dev_buf) % kAlign) return fail(DSM_EINVAL, "dev_buf must be 256-byte aligned");
+    const Layout L = make_layout(p);
+    if (dev_bytes < L.total)
+        return fail(DSM_ENOMEM, "device buffer too small: need " + std::to_string(L.total) + " bytes");
+    dsm_sim* s = new (std::nothrow) dsm_sim();
+    if (!s) return fail(DSM_EINVAL, "host allocation failed");
+    s->p = *p;
+    s->Q = lattice_q(p->dim);
+    s->N = (long long)p->nx * p->ny * p->nz;
+    if (p->dim == 2)
+        s->geom = Geom{p->nx, 1, p->ny, s->N};
+    else
+        s->geom = Geom{p->nx, p->ny, p->nz, s->N};
+    s->stream = (hipStream_t)stream;
+    char* base = (char*)dev_buf;
+    for (int k = 0; k < 2; ++k) {
+        s->d.f[k] = (float*)(base + L.off_f[k]);
+        s->d.g[k] = (float*)(base + L.off_g[k]);
+    }
+    s->d.c1 = (float*)(base + L.off_c1);
+    s->d.mask = (uint8_t*)(base + L.off_mask);
+    s->d.phi = (float*)(base + L.off_phi);
+    s->d.mu = (float*)(base + L.off_mu);
+    s->d.aux = (float*)(base + L.off_aux);
+    s->d.partials = (double*)(base + L.off_part);
+    s->d.red = (double*)(base + L.off_red);
+    s->d.flag = (int*)(base + L.off_flag);
+    s->cur = 0;
+    s->pull = 0;
+    s->stage = 0;
+    s->steps = 0;
+    s->beta = s->omega = 0.0;
+    s->tau_s = 1.0;
+    s->taug_s = 1.0;
+    s->tile_variant = 0;
+    s->tile_planes = 16;
+    auto cleanup = [&](int rc) {
+        delete s;
+        return rc;
+    };
+    const size_t N = (size_t)s->N;
+    std::vector<uint8_t> m(N, 0);
+    if (mask)
+        for (size_t n = 0; n < N; ++n) m[n] = mask[n] ? 1 : 0;
+    hipError_t e = hipMemcpyAsync(s->d.mask, m.data(), N, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_c1_from_mask(s->d.mask, s->d.c1, s->N, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return cleanup(fail(DSM_EDEVICE, std::string("dsm_create: ") + hipGetErrorString(e)));
+    *out = s;
+    return DSM_OK;
+}
+
+int dsm_init_solid(dsm_sim* s, int n_steps, double beta, double omega, double tau_s, double mobility_s,
+                   int flags) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (n_steps < 0) return fail(DSM_EINVAL, "n_steps must be >= 0");
+    if (!(beta >= 0.0) || !(omega >= 0.0) || !isfinite(beta) || !isfinite(omega))
+        return fail(DSM_EINVAL, "beta and omega must be finite and >= 0");
+    if (!(tau_s > 0.5) || !(mobility_s > 0.0)) return fail(DSM_EINVAL, "tau_s must be > 1/2, mobility_s > 0");
+    if (flags & ~(DSM_SOLID_RESET | DSM_SOLID_REMASK)) return fail(DSM_EINVAL, "unknown flags");
+    s->beta = beta;
+    s->omega = omega;
+    s->tau_s = tau_s;
+    s->taug_s = 0.5 + 3.0 * mobility_s;
+    if ((flags & DSM_SOLID_RESET) || s->stage != 1) {
+        s->stage = 1;
+        HIP_TRY(launch_c1_from_mask(s->d.mask, s->d.phi, s->N, s->stream));
+        int rc = init_populations(s, 1);
+        if (rc) return rc;
+    }
+    for (int t = 0; t < n_steps; ++t) {
+        int rc = one_step(s);
+        if (rc) return rc;
+    }
+    // freeze C1 = sum of the solid-stage g
+    HIP_TRY(launch_moment(s->p.dim, s->geom, s->d.g[s->cur], s->d.c1, s->pull, s->stream));
+    if (flags & DSM_SOLID_REMASK) HIP_TRY(launch_remask(s->d.c1, s->d.mask, s->N, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    int rc = check_flag(s);
+    return rc;
+}
+
+int dsm_set_solid_field(dsm_sim* s, const double* C1) {
+    if (!s || !C1) return fail(DSM_EINVAL, "NULL argument");
+    int rc = upload_field(s, C1, s->d.c1);
+    if (rc) return rc;
+    s->stage = 0;
+    return DSM_OK;
+}
+
+int dsm_set_liquid(dsm_sim* s, const double* C2) {
+    if (!s || !C2) return fail(DSM_EINVAL, "NULL argument");
+    if (s->stage == 1) {
+        // leaving the solid stage: C1 already frozen by dsm_init_solid
+    }
+    int rc = upload_field(s, C2, s->d.phi);
+    if (rc) return rc;
+    s->stage = 2;
+    s->steps = 0;
+    HIP_TRY(hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream));
+    return init_populations(s, 2);
+}
+
+int dsm_set_gravity(dsm_sim* s, const double g[3]) {
+    if (!s || !g) return fail(DSM_EINVAL, "NULL argument");
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(g[k])) return fail(DSM_EINVAL, "gravity must be finite");
+    if (s->p.dim == 2 && g[2] != 0.0) return fail(DSM_EINVAL, "gravity[2] must be 0 when dim == 2");
+    for (int k = 0; k < 3; ++k) s->p.gravity[k] = g[k];
+    return DSM_OK;
+}
+
+int dsm_step(dsm_sim* s, int n) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (n < 0) return fail(DSM_EINVAL, "n must be >= 0");
+    if (s->stage != 2) return fail(DSM_ESTATE, "dsm_step needs a liquid (dsm_set_liquid) first");
+    for (int t = 0; t < n; ++t) {
+        int rc = one_step(s);
+        if (rc) return rc;
+        ++s->steps;
+        if (s->p.reduce_every > 0 && s->steps % s->p.reduce_every == 0) {
+            rc = check_flag(s);
+            if (rc) return rc;
+        }
+    }
+    return DSM_OK;
+}
+
+int dsm_free_energy(dsm_sim* s, double* F, double* E_kin) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    double r[RED_SLOTS];
+    int rc = reduce(s, r);
+    if (rc) return rc;
+    if (F) *F = r[RED_FREE];
+    if (E_kin) *E_kin = r[RED_EKIN];
+    return DSM_OK;
+}
+
+int dsm_mass(dsm_sim* s, double m[3]) {
+    if (!s || !m) return fail(DSM_EINVAL, "NULL argument");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    double r[RED_SLOTS];
+    int rc = reduce(s, r);
+    if (rc) return rc;
+    m[0] = r[RED_C1];
+    m[1] = r[RED_C2];
+    m[2] = r[RED_C3];
+    return DSM_OK;
+}
+
+int dsm_fields(dsm_sim* s, double* C1, double* C2, double* C3, double* u, double* p) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    int rc = observe(s);
+    if (rc) return rc;
+    const size_t N = (size_t)s->N;
+    std::vector<double> c1(N), phi(N);
+    rc = download_field(s, s->stage == 2 ? s->d.c1 : s->d.phi, c1.data(), N);
+    if (rc) return rc;
+    if (s->stage == 2) {
+        rc = download_field(s, s->d.phi, phi.data(), N);
+        if (rc) return rc;
+    }
+    for (size_t n = 0; n < N; ++n) {
+        double a = c1[n], b = s->stage == 2 ? phi[n] : 0.0;
+        if (C1) C1[n] = a;
+        if (C2) C2[n] = b;
+        if (C3) C3[n] = 1.0 - a - b;
+    }
+    if (u) {
+        rc = download_field(s, s->d.aux, u, (size_t)s->p.dim * N);
+        if (rc) return rc;
+    }
+    if (p) {
+        rc = download_field(s, s->d.aux + 3 * N, p, N);
+        if (rc) return rc;
+    }
+    return DSM_OK;
+}
+
+int dsm_chemical_potential(dsm_sim* s, double* mu) {
+    if (!s || !mu) return fail(DSM_EINVAL, "NULL argument");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    int rc = observe(s);
+    if (rc) return rc;
+    return download_field(s, s->d.mu, mu, (size_t)s->N);
+}
+
+int dsm_get_populations(dsm_sim* s, double* f, double* g) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    const size_t QN = (size_t)s->Q * (size_t)s->N;
+    const float* fs = s->d.f[s->cur];
+    const float* gs = s->d.g[s->cur];
+    if (s->pull) {
+        const Phys ph = make_phys(s, s->stage);
+        const int o = 1 - s->cur;  // the spare pair is free between steps
+        HIP_TRY(launch_pull_state(s->p.dim, s->geom, ph, s->d.f[s->cur], s->d.g[s->cur], s->d.c1, s->d.f[o],
+                                  s->d.g[o], s->stream));
+        fs = s->d.f[o];
+        gs = s->d.g[o];
+    }
+    int rc = DSM_OK;
+    if (f) rc = download_field(s, fs, f, QN);
+    if (!rc && g) rc = download_field(s, gs, g, QN);
+    return rc;
+}
+
+static int upload_pops(dsm_sim* s, const double* f, const double* g, int pair) {
+    const size_t QN = (size_t)s->Q * (size_t)s->N;
+    s->stage_buf.resize(QN);
+    for (size_t k = 0; k < QN; ++k) s->stage_buf[k] = (float)f[k];
+    HIP_TRY(hipMemcpyAsync(s->d.f[pair], s->stage_buf.data(), QN * sizeof(float), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t k = 0; k < QN; ++k) s->stage_buf[k] = (float)g[k];
+    HIP_TRY(hipMemcpyAsync(s->d.g[pair], s->stage_buf.data(), QN * sizeof(float), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return DSM_OK;
+}
+
+int dsm_set_populations(dsm_sim* s, const double* f, const double* g) {
+    if (!s || !f || !g) return fail(DSM_EINVAL, "NULL argument");
+    int rc = upload_pops(s, f, g, 0);
+    if (rc) return rc;
+    if (s->stage == 0) s->stage = 2;
+    s->cur = 0;
+    s->pull = 0;
+    return DSM_OK;
+}
+
+int dsm_set_postcollision(dsm_sim* s, const double* fs, const double* gs) {
+    if (!s || !fs || !gs) return fail(DSM_EINVAL, "NULL argument");
+    int rc = upload_pops(s, fs, gs, 0);
+    if (rc) return rc;
+    if (s->stage == 0) s->stage = 2;
+    s->cur = 0;
+    s->pull = 1;
+    return DSM_OK;
+}
+
+size_t dsm_state_bytes(const dsm_sim* s) {
+    if (!s) return 0;
+    const size_t N = (size_t)s->N, Q = (size_t)s->Q;
+    return sizeof(StateHeader) + 2 * Q * N * sizeof(float) + N * sizeof(float) + N;
+}
+
+int dsm_get_state(dsm_sim* s, void* host, size_t bytes) {
+    if (!s || !host) return fail(DSM_EINVAL, "NULL argument");
+    if (bytes != dsm_state_bytes(s)) return fail(DSM_EINVAL, "state size mismatch");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    StateHeader h;
+    memset(&h, 0, sizeof(h));
+    h.magic = kStateMagic;
+    h.version = 1;
+    h.dim = s->p.dim;
+    h.nx = s->p.nx;
+    h.ny = s->p.ny;
+    h.nz = s->p.nz;
+    h.stage = s->stage;
+    h.pull = s->pull;
+    h.steps = s->steps;
+    for (int k = 0; k < 3; ++k) h.gravity[k] = s->p.gravity[k];
+    h.beta = s->beta;
+    h.omega = s->omega;
+    h.tau_s = s->tau_s;
+    h.taug_s = s->taug_s;
+    char* o = (char*)host;
+    memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    const size_t N = (size_t)s->N, QN = (size_t)s->Q * N;
+    HIP_TRY(hipMemcpyAsync(o, s->d.f[s->cur], QN * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    o += QN * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(o, s->d.g[s->cur], QN * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    o += QN * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(o, s->d.c1, N * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    o += N * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(o, s->d.mask, N, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return DSM_OK;
+}
+
+int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
+    if (!s || !host) return fail(DSM_EINVAL, "NULL argument");
+    if (bytes != dsm_state_bytes(s)) return fail(DSM_EINVAL, "state size mismatch");
+    StateHeader h;
+    memcpy(&h, host, sizeof(h));
+    if (h.magic != kStateMagic || h.version != 1) return fail(DSM_EINVAL, "not a dsm state image");
+    if (h.dim != s->p.dim || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz)
+        return fail(DSM_EINVAL, "state image is for another lattice");
+    if (h.stage != 1 && h.stage != 2) return fail(DSM_EINVAL, "state image has no live stage");
+    const char* o = (const char*)host + sizeof(h);
+    const size_t N = (size_t)s->N, QN = (size_t)s->Q * N;
+    HIP_TRY(hipMemcpyAsync(s->d.f[0], o, QN * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    o += QN * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(s->d.g[0], o, QN * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    o += QN * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(s->d.c1, o, N * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    o += N * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(s->d.mask, o, N, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->cur = 0;
+    s->pull = h.pull;
+    s->stage = h.stage;
+    s->steps = h.steps;
+    for (int k = 0; k < 3; ++k) s->p.gravity[k] = h.gravity[k];
+    s->beta = h.beta;
+    s->omega = h.omega;
+    s->tau_s = h.tau_s;
+    s->taug_s = h.taug_s;
+    return DSM_OK;
+}
+
+long long dsm_step_count(const dsm_sim* s) { return s ? s->steps : -1; }
+
+int dsm_set_tiling(dsm_sim* s, int variant, int planes) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (variant < 0 || variant >= fused_tile_variants(s->p.dim))
+        return fail(DSM_EINVAL, "unknown tile variant");
+    if (planes < 1 || planes > 4096) return fail(DSM_EINVAL, "planes must be in [1, 4096]");
+    s->tile_variant = variant;
+    s->tile_planes = planes;
+    return DSM_OK;
+}
+
+int dsm_tiling_variants(int dim) { return (dim == 2 || dim == 3) ? fused_tile_variants(dim) : 0; }
+
+int dsm_destroy(dsm_sim* s) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    hipError_t e = hipStreamSynchronize(s->stream);
+    delete s;
+    if (e != hipSuccess) return fail(DSM_EDEVICE, std::string("dsm_destroy: ") + hipGetErrorString(e));
+    return DSM_OK;
+}
+
+const char* dsm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

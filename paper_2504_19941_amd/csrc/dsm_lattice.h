@@ -1,0 +1,72 @@
+// dsm_lattice.h -- device-side lattice descriptions and small helpers for the
+// gfx950 kernels of libdsm.so.
+//
+// D2Q9 is the velocity set and weight vector of Sec. II.B; D3Q19 is used for
+// 3D.  Both list the rest velocity first and then each velocity next to its
+// opposite, so opp(i) = i + 1 for odd i and i - 1 for even i > 0.
+//
+// The 2D lattice is laid out as a 3D one with ny = 1: a 2D node (x, y) is
+// stored at x + nx*y, i.e. the 3D position (x, 0, y), and a D2Q9 velocity
+// (cx, cy) acts as (cx, 0, cy).  Every kernel is therefore written once for
+// "planes" along the slowest axis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsm {
+
+template <int D>
+struct Lattice;
+
+template <>
+struct Lattice<2> {
+    static constexpr int Q = 9;
+    // components along the stored (x, y, z) axes: D2Q9's y is the stored z
+    static constexpr int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int cy[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int cz[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr float w[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
+                                   1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+};
+
+template <>
+struct Lattice<3> {
+    static constexpr int Q = 19;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr float w[19] = {1.f / 3.f,
+                                    1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f,
+                                    1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
+                                    1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+};
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// Storage geometry: X fastest, Z slowest.  For dim 2, Y == 1.
+struct Geom {
+    int X, Y, Z;
+    long long N;  // X*Y*Z
+};
+
+// Physical and scheme parameters in the form the kernels use them.
+struct Phys {
+    float k1, k2, k3;    // kappa_1..3
+    float a2;            // alpha^2
+    float alpha;
+    float inv_tau;       // 1 / tau
+    float inv_taug;      // 1 / tau_g
+    float fpref;         // 1 - 1 / (2 tau)
+    float grav[3];       // body force per unit liquid (stored axes)
+    float beta, omega;   // solid stage
+    int stage;           // 1 = solid stage (C1 evolves), 2 = fluid stage (C2 evolves)
+};
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__device__ __forceinline__ long long node_index(const Geom& g, int x, int y, int z) {
+    return (long long)x + (long long)g.X * ((long long)y + (long long)g.Y * (long long)z);
+}
+
+}  // namespace dsm

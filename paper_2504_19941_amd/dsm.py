@@ -1,0 +1,325 @@
+"""Python binding of libdsm.so (include/dsm.h): argument marshalling only.
+
+Every function named ``dsm_*`` here calls the C function of the same name;
+all lattice work runs in the library's HIP kernels.  PyTorch supplies the
+device buffer and the stream, nothing else.  If libdsm.so has not been built
+this module raises on first use: there is no fallback implementation.
+
+:class:`Simulation` bundles a handle with its device buffer.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdsm.so")
+
+DSM_OK, DSM_EINVAL, DSM_ENOMEM, DSM_EDEVICE, DSM_EUNSTABLE, DSM_ESTATE = 0, -1, -2, -3, -4, -5
+DSM_SOLID_RESET, DSM_SOLID_REMASK = 1, 2
+DSM_KERNEL_FUSED, DSM_KERNEL_SPLIT = 0, 1
+
+EXPORTED = [
+    "dsm_required_bytes", "dsm_create", "dsm_init_solid", "dsm_set_solid_field", "dsm_set_liquid",
+    "dsm_set_gravity", "dsm_step", "dsm_free_energy", "dsm_mass", "dsm_fields",
+    "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
+    "dsm_state_bytes", "dsm_get_state", "dsm_set_state", "dsm_step_count", "dsm_set_tiling",
+    "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
+]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class dsm_params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("kappa", ctypes.c_double * 3), ("alpha", ctypes.c_double), ("tau", ctypes.c_double),
+        ("mobility", ctypes.c_double), ("gravity", ctypes.c_double * 3),
+        ("reduce_every", ctypes.c_int), ("kernel", ctypes.c_int),
+    ]
+
+
+class DsmError(RuntimeError):
+    def __init__(self, code, what, msg):
+        super().__init__(f"{what} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libdsm.so and declares its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libdsm.so not found at {path}: build it with "
+                           "`python -m paper_2504_19941_amd.build` (no fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.dsm_required_bytes.argtypes = [ctypes.POINTER(dsm_params)]
+    lib.dsm_required_bytes.restype = ctypes.c_size_t
+    lib.dsm_create.argtypes = [ctypes.POINTER(dsm_params), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.dsm_init_solid.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int]
+    lib.dsm_set_solid_field.argtypes = [vp, _dp]
+    lib.dsm_set_liquid.argtypes = [vp, _dp]
+    lib.dsm_set_gravity.argtypes = [vp, _dp]
+    lib.dsm_step.argtypes = [vp, ctypes.c_int]
+    lib.dsm_free_energy.argtypes = [vp, _dp, _dp]
+    lib.dsm_mass.argtypes = [vp, _dp]
+    lib.dsm_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    lib.dsm_chemical_potential.argtypes = [vp, _dp]
+    lib.dsm_get_populations.argtypes = [vp, _dp, _dp]
+    lib.dsm_set_populations.argtypes = [vp, _dp, _dp]
+    lib.dsm_set_postcollision.argtypes = [vp, _dp, _dp]
+    lib.dsm_state_bytes.argtypes = [vp]
+    lib.dsm_state_bytes.restype = ctypes.c_size_t
+    lib.dsm_get_state.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.dsm_set_state.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.dsm_step_count.argtypes = [vp]
+    lib.dsm_step_count.restype = ctypes.c_longlong
+    lib.dsm_set_tiling.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.dsm_tiling_variants.argtypes = [ctypes.c_int]
+    lib.dsm_destroy.argtypes = [vp]
+    lib.dsm_last_error.argtypes = []
+    lib.dsm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc, what):
+    if rc != DSM_OK:
+        raise DsmError(rc, what, dsm_last_error())
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+
+
+# ---------------------------------------------------------------------------
+# one function per C entry point
+
+def make_params(dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
+                reduce_every=0, kernel=DSM_KERNEL_FUSED) -> dsm_params:
+    p = dsm_params()
+    p.dim = int(dim)
+    p.nx, p.ny = int(shape[0]), int(shape[1])
+    p.nz = int(shape[2]) if dim == 3 else 1
+    p.kappa[:] = [float(k) for k in kappa]
+    p.alpha, p.tau, p.mobility = float(alpha), float(tau), float(mobility)
+    g = list(gravity) + [0.0] * (3 - len(gravity))
+    p.gravity[:] = [float(v) for v in g]
+    p.reduce_every, p.kernel = int(reduce_every), int(kernel)
+    return p
+
+
+def dsm_required_bytes(params: dsm_params) -> int:
+    return int(load().dsm_required_bytes(ctypes.byref(params)))
+
+
+def dsm_create(params: dsm_params, mask, dev_ptr: int, dev_bytes: int, stream: int):
+    m = None
+    if mask is not None:
+        m = np.ascontiguousarray(np.asarray(mask).reshape(-1), dtype=np.uint8)
+    h = ctypes.c_void_p()
+    rc = load().dsm_create(ctypes.byref(params), None if m is None else m.ctypes.data_as(ctypes.c_void_p),
+                           ctypes.c_void_p(dev_ptr), ctypes.c_size_t(dev_bytes), ctypes.c_void_p(stream),
+                           ctypes.byref(h))
+    _check(rc, "dsm_create")
+    return h
+
+
+def dsm_init_solid(h, n_steps, beta, omega, tau_s=1.0, mobility_s=1.0 / 6.0, flags=DSM_SOLID_RESET):
+    _check(load().dsm_init_solid(h, int(n_steps), float(beta), float(omega), float(tau_s), float(mobility_s),
+                                 int(flags)), "dsm_init_solid")
+
+
+def dsm_set_solid_field(h, C1):
+    a = _f64(C1)
+    _check(load().dsm_set_solid_field(h, _p(a)), "dsm_set_solid_field")
+
+
+def dsm_set_liquid(h, C2):
+    a = _f64(C2)
+    _check(load().dsm_set_liquid(h, _p(a)), "dsm_set_liquid")
+
+
+def dsm_set_gravity(h, g):
+    a = _f64(list(g) + [0.0] * (3 - len(g)))
+    _check(load().dsm_set_gravity(h, _p(a)), "dsm_set_gravity")
+
+
+def dsm_step(h, n):
+    _check(load().dsm_step(h, int(n)), "dsm_step")
+
+
+def dsm_free_energy(h):
+    F, E = ctypes.c_double(), ctypes.c_double()
+    _check(load().dsm_free_energy(h, ctypes.byref(F), ctypes.byref(E)), "dsm_free_energy")
+    return F.value, E.value
+
+
+def dsm_mass(h):
+    m = np.zeros(3)
+    _check(load().dsm_mass(h, _p(m)), "dsm_mass")
+    return m
+
+
+def dsm_fields(h, N, dim):
+    C1, C2, C3, p = (np.zeros(N) for _ in range(4))
+    u = np.zeros(dim * N)
+    _check(load().dsm_fields(h, _p(C1), _p(C2), _p(C3), _p(u), _p(p)), "dsm_fields")
+    return {"C1": C1, "C2": C2, "C3": C3, "u": u.reshape(dim, N), "p": p}
+
+
+def dsm_chemical_potential(h, N):
+    mu = np.zeros(N)
+    _check(load().dsm_chemical_potential(h, _p(mu)), "dsm_chemical_potential")
+    return mu
+
+
+def dsm_get_populations(h, Q, N):
+    f = np.zeros((Q, N))
+    g = np.zeros((Q, N))
+    _check(load().dsm_get_populations(h, _p(f), _p(g)), "dsm_get_populations")
+    return f, g
+
+
+def dsm_set_populations(h, f, g):
+    f, g = _f64(f), _f64(g)
+    _check(load().dsm_set_populations(h, _p(f), _p(g)), "dsm_set_populations")
+
+
+def dsm_set_postcollision(h, fs, gs):
+    fs, gs = _f64(fs), _f64(gs)
+    _check(load().dsm_set_postcollision(h, _p(fs), _p(gs)), "dsm_set_postcollision")
+
+
+def dsm_state_bytes(h) -> int:
+    return int(load().dsm_state_bytes(h))
+
+
+def dsm_get_state(h) -> bytes:
+    n = dsm_state_bytes(h)
+    buf = ctypes.create_string_buffer(n)
+    _check(load().dsm_get_state(h, buf, n), "dsm_get_state")
+    return buf.raw
+
+
+def dsm_set_state(h, state: bytes):
+    buf = ctypes.create_string_buffer(state, len(state))
+    _check(load().dsm_set_state(h, buf, len(state)), "dsm_set_state")
+
+
+def dsm_step_count(h) -> int:
+    return int(load().dsm_step_count(h))
+
+
+def dsm_set_tiling(h, variant, planes):
+    _check(load().dsm_set_tiling(h, int(variant), int(planes)), "dsm_set_tiling")
+
+
+def dsm_tiling_variants(dim) -> int:
+    return int(load().dsm_tiling_variants(int(dim)))
+
+
+def dsm_destroy(h):
+    _check(load().dsm_destroy(h), "dsm_destroy")
+
+
+def dsm_last_error() -> str:
+    return load().dsm_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+
+class Simulation:
+    """A libdsm.so handle together with the torch device buffer it lives in."""
+
+    def __init__(self, dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
+                 mask=None, reduce_every=0, kernel=DSM_KERNEL_FUSED, device="cuda:0", stream=None):
+        import torch
+
+        self.dim = dim
+        self.shape = tuple(shape)
+        self.params = make_params(dim, shape, kappa, alpha, tau, mobility, gravity, reduce_every, kernel)
+        self.N = int(self.params.nx * self.params.ny * self.params.nz)
+        self.Q = 9 if dim == 2 else 19
+        self.nbytes = dsm_required_bytes(self.params)
+        if self.nbytes == 0:
+            raise DsmError(DSM_EINVAL, "dsm_required_bytes", "invalid parameters")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # over-allocate by 256 bytes so the handle's base can be 256-byte aligned
+        self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.buffer.data_ptr()
+        self.base = (base + 255) // 256 * 256
+        self.handle = dsm_create(self.params, mask, self.base, self.nbytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            dsm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_solid(self, n_steps, beta, omega, tau_s=1.0, mobility_s=1.0 / 6.0, flags=DSM_SOLID_RESET):
+        dsm_init_solid(self.handle, n_steps, beta, omega, tau_s, mobility_s, flags)
+
+    def set_solid_field(self, C1):
+        dsm_set_solid_field(self.handle, C1)
+
+    def set_liquid(self, C2):
+        dsm_set_liquid(self.handle, C2)
+
+    def set_gravity(self, g):
+        dsm_set_gravity(self.handle, g)
+
+    def step(self, n):
+        dsm_step(self.handle, n)
+
+    def free_energy(self):
+        return dsm_free_energy(self.handle)
+
+    def mass(self):
+        return dsm_mass(self.handle)
+
+    def fields(self):
+        return dsm_fields(self.handle, self.N, self.dim)
+
+    def chemical_potential(self):
+        return dsm_chemical_potential(self.handle, self.N)
+
+    def get_populations(self):
+        return dsm_get_populations(self.handle, self.Q, self.N)
+
+    def set_populations(self, f, g):
+        dsm_set_populations(self.handle, f, g)
+
+    def set_postcollision(self, fs, gs):
+        dsm_set_postcollision(self.handle, fs, gs)
+
+    def get_state(self) -> bytes:
+        return dsm_get_state(self.handle)
+
+    def set_state(self, state: bytes):
+        dsm_set_state(self.handle, state)
+
+    def set_tiling(self, variant, planes):
+        dsm_set_tiling(self.handle, variant, planes)
+
+    @property
+    def steps(self) -> int:
+        return dsm_step_count(self.handle)
