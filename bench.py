@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the diffuse-solid ternary lattice Boltzmann step on one GPU.
+
+One "step" is one fluid-stage time step of the whole lattice (Sec. II.B of
+the paper: stream g and take its moment, chemical potential, forces, stream f
+with interpolated bounce-back, velocity, both collisions), run by the fused
+gfx950 kernel of libdsm.so through its C ABI.
+
+Default workload: D3Q19 128^3 periodic box, 6-node diffuse solid slab
+(analytic tanh edge, alpha = 1), hemispherical liquid drop of radius 30 on
+it, kappa for a 90 degree Young angle (gamma_12 = gamma_23 = 2.5e-3),
+tau = 1, M = 0.1, FP32 populations.  Inputs are resident in HBM when the timed
+region starts.
+
+Prints ONE JSON line with MLUPS, the roofline of the fused kernel (HBM bytes
+per lattice update over its event-timed duration), the HBM traffic measured
+by rocprofv3 counters when the committed counter summary still matches the
+kernel source, and the FP64 CPU oracle timed on this host as a baseline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+METRIC = "MLUPS and HBM GB/s (% peak), FP32 vs FP16-store; p50/p99 job latency"
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "fused_step_d3q19_128cube_pmc.md")
+KERNEL_SOURCES = ["dsm_fused.hip", "dsm_lattice.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_19941_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_lup(Q: int, pop_bytes: int) -> int:
+    """Algorithmic HBM bytes of one lattice update: every f and g population
+    read once and written once, plus one read of the frozen solid field C1."""
+    return 2 * 2 * Q * pop_bytes + 4
+
+
+def measured_traffic(workload: str, nodes: int):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the factor measured on
+    a plain copy kernel), or None if absent or taken on other kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+
+    def field(name):
+        m = re.search(rf"^{name}:\s*(\S+)", text, re.M)
+        return m.group(1) if m else None
+
+    if field("workload") != workload or field("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(field("hbm_bytes_per_launch"))
+    except (TypeError, ValueError):
+        return None
+
+
+def cpu_baseline(w, seconds: float):
+    """The FP64 oracle on this host's cores, on the same lattice, for about
+    ``seconds`` of CPU work."""
+    from oracle.oracle import Oracle
+    from paper_2504_19941_amd import workloads as W
+
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    threads = max(1, min(threads, 16))
+    o = Oracle(w.dim, w.shape, w.kappa, tau=w.tau, mobility=w.mobility, threads=threads)
+    o.set_solid_field(W.flat(w.C1))
+    o.set_liquid(W.flat(w.C2))
+    t0 = time.perf_counter()
+    o.step(1)
+    dt = time.perf_counter() - t0
+    more = max(0, int(math.ceil(seconds / max(dt, 1e-6))) - 1)
+    t0 = time.perf_counter()
+    if more:
+        o.step(more)
+    dt_more = time.perf_counter() - t0
+    steps, total = (more, dt_more) if more else (1, dt)
+    o.close()
+    return {
+        "value": round(w.nodes * steps / total / 1e6, 4),
+        "unit": "MLUPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{w.name}: {steps} FP64 oracle steps after 1 untimed, {threads} OpenMP threads, "
+                  f"{total:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--theta", type=float, default=90.0)
+    ap.add_argument("--tile", type=int, default=None, help="fused-kernel tile variant")
+    ap.add_argument("--planes", type=int, default=None, help="planes marched per workgroup")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, run 3 plain device copies of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU only "
+              "(the single-GPU step; see the sharding design for more)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2504_19941_amd import dsm
+    from paper_2504_19941_amd import workloads as W
+
+    dsm.load()  # raises if libdsm.so is missing: there is no fallback
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    w = W.config_3d_sessile(args.theta, n=128)
+    Q = 19
+    sim = dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
+                         reduce_every=0, device=dev)
+    if args.tile is not None or args.planes is not None:
+        sim.set_tiling(args.tile or 0, args.planes or 16)
+    sim.set_solid_field(W.flat(w.C1))
+    sim.set_liquid(W.flat(w.C2))
+    fluid_frac = float((w.C1 <= 0.5).mean())
+    m0 = sim.mass()
+    stream = sim.stream
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = e0.elapsed_time(e1)
+    ms = ms_total / max(args.steps, 1)
+    m1 = sim.mass()
+    drift = abs(m1[1] - m0[1]) / abs(m0[1])
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    N = w.nodes
+    mlups = N / (ms * 1e-3) / 1e6
+    bpl = bytes_per_lup(Q, 4)
+    achieved = bpl * N / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name, N)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "lattice": "D3Q19",
+            "shape": list(w.shape),
+            "storage": "fp32",
+            "fluid_node_fraction": round(fluid_frac, 4),
+            "tau": w.tau,
+            "mobility": w.mobility,
+            "kappa": [round(k, 8) for k in w.kappa],
+        },
+        "hbm_GBps": round(achieved, 1),
+        "hbm_frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "liquid_mass_drift_rel": drift,
+        "wall_s_timed": round(wall, 4),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "bytes_per_lup": bpl,
+            "kernel": "k_step_fused<3,...> (one launch per step)",
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

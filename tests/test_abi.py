@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: libdsm.so loads, exports every function that
+include/dsm.h declares, sizes its device buffer, and rejects invalid
+arguments before it issues any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2504_19941_amd import dsm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dsm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(dsm_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dsm.LIB_PATH):
+        from paper_2504_19941_amd import build
+
+        build.build()
+    return dsm.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dsm_create", "dsm_step", "dsm_free_energy", "dsm_fields", "dsm_mass",
+                     "dsm_init_solid", "dsm_set_liquid", "dsm_destroy", "dsm_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in include/dsm.h but not exported"
+    assert sorted(dsm.EXPORTED) == sorted(declared_functions())
+
+
+def good_params(**kw):
+    p = dsm.make_params(3, (32, 24, 16), (0.01, 0.005, 0.01))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_required_bytes_matches_layout(lib):
+    p = good_params()
+    N = 32 * 24 * 16
+    need = dsm.dsm_required_bytes(p)
+    # four FP32 population sets of 19 planes dominate the buffer
+    assert need >= 4 * 19 * N * 4 + N * 4 + N
+    assert need < 4 * 19 * N * 4 + 12 * N * 4 + (1 << 20)
+    p2 = dsm.make_params(2, (64, 32), (0.01, 0.005, 0.01))
+    assert dsm.dsm_required_bytes(p2) >= 4 * 9 * 64 * 32 * 4
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 4), ("nx", 3), ("nz", 2), ("tau", 0.5), ("tau", float("nan")), ("mobility", 0.0),
+    ("alpha", 0.0), ("reduce_every", -1), ("kernel", 7),
+])
+def test_invalid_params_rejected_on_host(lib, field, value):
+    p = good_params(**{field: value})
+    assert dsm.dsm_required_bytes(p) == 0
+    h = ctypes.c_void_p()
+    rc = lib.dsm_create(ctypes.byref(p), None, ctypes.c_void_p(256), ctypes.c_size_t(1 << 40), None,
+                        ctypes.byref(h))
+    assert rc == dsm.DSM_EINVAL
+    assert h.value is None
+    assert dsm.dsm_last_error() != ""
+
+
+def test_negative_kappa_and_zero_fluid_kappa(lib):
+    p = good_params()
+    p.kappa[0] = -1.0
+    assert dsm.dsm_required_bytes(p) == 0
+    p = good_params()
+    p.kappa[1] = p.kappa[2] = 0.0
+    assert dsm.dsm_required_bytes(p) == 0
+
+
+def test_small_or_misaligned_buffer_rejected(lib):
+    p = good_params()
+    need = dsm.dsm_required_bytes(p)
+    h = ctypes.c_void_p()
+    rc = lib.dsm_create(ctypes.byref(p), None, ctypes.c_void_p(4096), ctypes.c_size_t(need - 1), None,
+                        ctypes.byref(h))
+    assert rc == dsm.DSM_ENOMEM
+    assert "too small" in dsm.dsm_last_error()
+    rc = lib.dsm_create(ctypes.byref(p), None, ctypes.c_void_p(4096 + 8), ctypes.c_size_t(need), None,
+                        ctypes.byref(h))
+    assert rc == dsm.DSM_EINVAL
+    rc = lib.dsm_create(ctypes.byref(p), None, None, ctypes.c_size_t(need), None, ctypes.byref(h))
+    assert rc == dsm.DSM_EINVAL
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.dsm_step(None, 1) == dsm.DSM_EINVAL
+    assert lib.dsm_destroy(None) == dsm.DSM_EINVAL
+    assert lib.dsm_free_energy(None, None, None) == dsm.DSM_EINVAL
+    assert lib.dsm_tiling_variants(3) >= 1
+    assert lib.dsm_tiling_variants(5) == 0
