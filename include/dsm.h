@@ -172,12 +172,12 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes);
 long long dsm_step_count(const dsm_sim* s);
 
 /* Launch shape of the fused step kernel: the workgroup tile (variant in
- * [0, dsm_tiling_variants(dim)); 3D: 0 = 32x8, 1 = 64x4, 2 = 64x8, 3 = 32x16
- * columns; 2D: 0 = 128, 1 = 256, 2 = 64 columns) and the number of planes
- * (1..4096) each workgroup marches through along the slowest axis.  Results
- * do not depend on it beyond round-off-free reordering of independent nodes:
- * every choice computes bit-identical populations.  Defaults: variant 0,
- * 16 planes.  Errors: DSM_EINVAL. */
+ * [0, dsm_tiling_variants(dim)); 3D: 0 = 64x4, 1 = 64x8, 2 = 128x4 columns;
+ * 2D: 0 = 256, 1 = 128, 2 = 64 columns) and the number of planes (1..4096)
+ * each workgroup marches through along the slowest axis.  Every choice
+ * computes bit-identical populations (each node's arithmetic does not depend
+ * on the tile).  Defaults: 3D variant 2, 2D variant 0, 16 planes.
+ * Errors: DSM_EINVAL. */
 int dsm_set_tiling(dsm_sim* s, int variant, int planes);
 int dsm_tiling_variants(int dim);
 

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdsm.so")
-SOURCES = ["dsm_api.hip", "dsm_kernels.hip", "dsm_fused.hip"]
+SOURCES = ["dsm_api.hip", "dsm_kernels.hip", "dsm_fused.hip", "dsm_links.hip"]
 ARCH = "gfx950"
 
 

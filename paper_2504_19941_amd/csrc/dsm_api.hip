@@ -46,7 +46,9 @@ const char* validate(const dsm_params* p) {
     if (p->dim == 2 && p->nz != 1) return "nz must be 1 when dim == 2";
     if (p->dim == 3 && p->nz < 4) return "nz must be >= 4 when dim == 3";
     const double nodes = (double)p->nx * (double)p->ny * (double)p->nz;
-    if (nodes > 2147483647.0) return "lattice has more than 2^31 - 1 nodes";
+    if (nodes * lattice_q(p->dim) > 4294967295.0) return "lattice has more than 2^32 - 1 populations";
+    if ((double)p->nx * (double)(p->dim == 3 ? p->ny : 1) * lattice_q(p->dim) * 4.0 > 2147483647.0)
+        return "one lattice plane of populations exceeds 2 GiB";
     for (int k = 0; k < 3; ++k)
         if (!(p->kappa[k] >= 0.0) || !isfinite(p->kappa[k])) return "kappa must be finite and >= 0";
     if (!(p->kappa[1] + p->kappa[2] > 0.0)) return "kappa_2 + kappa_3 must be > 0";
@@ -62,7 +64,8 @@ const char* validate(const dsm_params* p) {
 }
 
 struct Layout {
-    size_t off_f[2], off_g[2], off_c1, off_mask, off_phi, off_mu, off_aux, off_part, off_red, off_flag;
+    size_t off_f[2], off_g[2], off_c1, off_mask, off_phi, off_mu, off_aux, off_part, off_red, off_flag, off_links,
+        off_ent, off_nlinks;
     size_t total;
 };
 
@@ -88,6 +91,9 @@ Layout make_layout(const dsm_params* p) {
     L.off_part = take((size_t)kReduceBlocks * RED_SLOTS * sizeof(double));
     L.off_red = take(RED_SLOTS * sizeof(double));
     L.off_flag = take(4 * sizeof(int));
+    L.off_ent = take(N * sizeof(int2));
+    L.off_links = take((size_t)kLinksPerNode * N * sizeof(LinkRec));
+    L.off_nlinks = take(4 * sizeof(int));
     L.total = o;
     return L;
 }
@@ -114,6 +120,7 @@ struct dsm_sim {
     int stage;     // 0: no live state, 1: solid stage live, 2: fluid stage live
     long long steps;
     double beta, omega, tau_s, taug_s;
+    int nlinks;        // boundary nodes with cut links (fluid stage)
     int tile_variant;  // workgroup tile of the fused step
     int tile_planes;   // planes marched per workgroup
     std::vector<float> stage_buf;  // host staging for conversions
@@ -164,6 +171,38 @@ int download_field(dsm_sim* s, const float* dev, double* host, size_t count) {
     return DSM_OK;
 }
 
+// Populations: host arrays are [Q][N] (direction-major planes of nodes); the
+// device stores them row-interleaved, (row*Q + i)*X + x with n = x + X*row.
+int download_pops(dsm_sim* s, const float* dev, double* host) {
+    const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
+    s->stage_buf.resize(Q * N);
+    HIP_TRY(hipMemcpyAsync(s->stage_buf.data(), dev, Q * N * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t r = 0; r < rows; ++r)
+        for (size_t i = 0; i < Q; ++i)
+            for (size_t x = 0; x < X; ++x) host[i * N + r * X + x] = (double)s->stage_buf[(r * Q + i) * X + x];
+    return DSM_OK;
+}
+
+int upload_pops_one(dsm_sim* s, const double* host, float* dev) {
+    const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
+    s->stage_buf.resize(Q * N);
+    for (size_t r = 0; r < rows; ++r)
+        for (size_t i = 0; i < Q; ++i)
+            for (size_t x = 0; x < X; ++x) s->stage_buf[(r * Q + i) * X + x] = (float)host[i * N + r * X + x];
+    HIP_TRY(hipMemcpyAsync(dev, s->stage_buf.data(), Q * N * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return DSM_OK;
+}
+
+// The fused step leaves f of solid nodes untouched (it is never read), so the
+// spare buffer pair is cleared whenever a new state is installed: every byte of
+// the state then depends only on the inputs.
+int clear_spare_f(dsm_sim* s, int spare) {
+    HIP_TRY(hipMemsetAsync(s->d.f[spare], 0, (size_t)s->Q * (size_t)s->N * sizeof(float), s->stream));
+    return DSM_OK;
+}
+
 // Observables of the live state into phi, mu and aux.
 int observe(dsm_sim* s) {
     const Phys ph = make_phys(s, s->stage);
@@ -186,11 +225,32 @@ int reduce(dsm_sim* s, double out[RED_SLOTS]) {
     return DSM_OK;
 }
 
+// Cut-link table of the fluid stage for the current C1.
+int build_links(dsm_sim* s) {
+    HIP_TRY(launch_find_links(s->p.dim, s->geom, s->d.c1, s->d.ent, s->d.nlinks, s->stream));
+    int count[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(count, s->d.nlinks, sizeof(count), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const long long cap = (long long)kLinksPerNode * s->N;
+    HIP_TRY(launch_build_links(s->p.dim, s->geom, s->p.alpha, s->d.c1, s->d.ent, count[0], s->d.links, cap,
+                               s->d.nlinks, s->stream));
+    HIP_TRY(hipMemcpyAsync(count, s->d.nlinks, sizeof(count), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->nlinks = 0;
+    if (count[1] > cap)
+        return fail(DSM_EINVAL, "solid surface has more cut links than the table holds (" +
+                                    std::to_string(count[1]) + " > " + std::to_string(cap) + ")");
+    s->nlinks = count[1];
+    return DSM_OK;
+}
+
 // One time step of the live stage: reads buffer pair cur, writes 1 - cur.
 int one_step(dsm_sim* s) {
     const Phys ph = make_phys(s, s->stage);
     const int c = s->cur, n = 1 - s->cur;
     if (s->p.kernel == DSM_KERNEL_FUSED) {
+        if (s->stage == 2 && s->pull)
+            HIP_TRY(launch_bounce(s->d.f[c], s->d.links, s->nlinks, s->stream));
         HIP_TRY(launch_step_fused(s->p.dim, s->geom, ph, s->d.f[c], s->d.g[c], s->d.f[n], s->d.g[n], s->d.c1,
                                   s->d.mask, s->pull, s->d.flag, s->tile_variant, s->tile_planes, s->stream));
     } else {
@@ -211,7 +271,7 @@ int init_populations(dsm_sim* s, int stage) {
     HIP_TRY(launch_init_populations(s->p.dim, s->geom, s->d.phi, s->d.mu, s->d.f[0], s->d.g[0], s->stream));
     s->cur = 0;
     s->pull = 0;
-    return DSM_OK;
+    return clear_spare_f(s, 1);
 }
 
 int check_flag(dsm_sim* s) {
@@ -264,6 +324,10 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     s->d.partials = (double*)(base + L.off_part);
     s->d.red = (double*)(base + L.off_red);
     s->d.flag = (int*)(base + L.off_flag);
+    s->d.ent = (int2*)(base + L.off_ent);
+    s->d.links = (LinkRec*)(base + L.off_links);
+    s->d.nlinks = (int*)(base + L.off_nlinks);
+    s->nlinks = 0;
     s->cur = 0;
     s->pull = 0;
     s->stage = 0;
@@ -271,7 +335,7 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     s->beta = s->omega = 0.0;
     s->tau_s = 1.0;
     s->taug_s = 1.0;
-    s->tile_variant = 0;
+    s->tile_variant = p->dim == 3 ? 2 : 0;
     s->tile_planes = 16;
     auto cleanup = [&](int rc) {
         delete s;
@@ -317,6 +381,7 @@ int dsm_init_solid(dsm_sim* s, int n_steps, double beta, double omega, double ta
     if (flags & DSM_SOLID_REMASK) HIP_TRY(launch_remask(s->d.c1, s->d.mask, s->N, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     int rc = check_flag(s);
+    if (!rc) rc = build_links(s);
     return rc;
 }
 
@@ -325,7 +390,7 @@ int dsm_set_solid_field(dsm_sim* s, const double* C1) {
     int rc = upload_field(s, C1, s->d.c1);
     if (rc) return rc;
     s->stage = 0;
-    return DSM_OK;
+    return build_links(s);
 }
 
 int dsm_set_liquid(dsm_sim* s, const double* C2) {
@@ -430,7 +495,6 @@ int dsm_chemical_potential(dsm_sim* s, double* mu) {
 int dsm_get_populations(dsm_sim* s, double* f, double* g) {
     if (!s) return fail(DSM_EINVAL, "sim is NULL");
     if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
-    const size_t QN = (size_t)s->Q * (size_t)s->N;
     const float* fs = s->d.f[s->cur];
     const float* gs = s->d.g[s->cur];
     if (s->pull) {
@@ -442,23 +506,16 @@ int dsm_get_populations(dsm_sim* s, double* f, double* g) {
         gs = s->d.g[o];
     }
     int rc = DSM_OK;
-    if (f) rc = download_field(s, fs, f, QN);
-    if (!rc && g) rc = download_field(s, gs, g, QN);
+    if (f) rc = download_pops(s, fs, f);
+    if (!rc && g) rc = download_pops(s, gs, g);
     return rc;
 }
 
 static int upload_pops(dsm_sim* s, const double* f, const double* g, int pair) {
-    const size_t QN = (size_t)s->Q * (size_t)s->N;
-    s->stage_buf.resize(QN);
-    for (size_t k = 0; k < QN; ++k) s->stage_buf[k] = (float)f[k];
-    HIP_TRY(hipMemcpyAsync(s->d.f[pair], s->stage_buf.data(), QN * sizeof(float), hipMemcpyHostToDevice,
-                           s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    for (size_t k = 0; k < QN; ++k) s->stage_buf[k] = (float)g[k];
-    HIP_TRY(hipMemcpyAsync(s->d.g[pair], s->stage_buf.data(), QN * sizeof(float), hipMemcpyHostToDevice,
-                           s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    return DSM_OK;
+    int rc = upload_pops_one(s, f, s->d.f[pair]);
+    if (!rc) rc = upload_pops_one(s, g, s->d.g[pair]);
+    if (!rc) rc = clear_spare_f(s, 1 - pair);
+    return rc;
 }
 
 int dsm_set_populations(dsm_sim* s, const double* f, const double* g) {
@@ -541,6 +598,7 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
     o += N * sizeof(float);
     HIP_TRY(hipMemcpyAsync(s->d.mask, o, N, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream));
+    HIP_TRY(hipMemsetAsync(s->d.f[1], 0, QN * sizeof(float), s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->cur = 0;
     s->pull = h.pull;
@@ -551,7 +609,7 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
     s->omega = h.omega;
     s->tau_s = h.tau_s;
     s->taug_s = h.taug_s;
-    return DSM_OK;
+    return build_links(s);
 }
 
 long long dsm_step_count(const dsm_sim* s) { return s ? s->steps : -1; }

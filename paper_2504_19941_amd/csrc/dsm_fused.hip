@@ -1,28 +1,39 @@
 // dsm_fused.hip -- the fused single-pass time step of libdsm.so (gfx950).
 //
-// One launch performs a whole step of Sec. II.B on every node: stream
-// (pull) the Cahn-Hilliard populations g and take their zeroth moment C,
-// the chemical potential from the isotropic Laplacians of C and C1, the
-// force mu grad C (+ body force), stream the hydrodynamic populations f with
+// One launch performs a whole step of Sec. II.B on every node: stream (pull)
+// the Cahn-Hilliard populations g and take their zeroth moment C, the
+// chemical potential from the isotropic Laplacians of C and C1, the force
+// mu grad C (+ body force), stream the hydrodynamic populations f with
 // interpolated bounce-back at the diffuse solid, velocity and pressure, and
-// both BGK collisions.  Populations are read once and written once.
+// both BGK collisions.  Every population is read once and written once.
 //
-// Dependencies: the collision at node x needs mu(x) and grad C(x), i.e. C on
-// the 1-ring of x, and every C is the sum of Q pulled g values.  Each
-// workgroup owns a TX x TY block of columns and marches along the slowest
-// axis through a chunk of TZ planes.  Per plane it
-//   A  pulls g for the block plus a 1-column halo and writes C (and the
-//      frozen C1) of that plane into 4-slot LDS rings; a column's own pulled
-//      g stay in registers until its collision one plane later;
-//   C  collides the plane behind, whose 1-ring of C and C1 is complete.
-// One barrier per plane suffices: A of the next plane writes a ring slot that
-// C of this plane does not read.  Only halo columns are recomputed (their
-// loads hit in L2, where neighbouring workgroups of the same XCD read the
-// same lines); along the march each chunk recomputes 1 + 1 warm-up planes.
+// Work decomposition.  The collision at node x needs mu(x) and grad C(x), so C
+// on the 1-ring of x; every C is the sum of Q pulled g values.  A workgroup
+// owns a tile of TY lattice rows x 64*TXW columns (one 64-lane wave per row
+// segment, so every wave-wide load of one direction is a contiguous run of
+// one row) and marches along the slowest axis through TZ planes.  Iteration j
+// works on two planes:
+//   phase 1: issue the f loads of the collision plane c = l - 1; pull g of the
+//            lead plane l for the own columns (kept in registers until their
+//            collision one iteration later) and for the 1-column halo; write
+//            C (and the frozen C1) of plane l into 4-slot LDS rings;
+//   barrier;
+//   phase 2: collide plane c, whose 1-ring of C and C1 is complete, and store.
+// The ring slots written by phase 1 of an iteration are never read by phase 2
+// of the iteration before or of the same iteration, so one barrier per plane
+// suffices.  Halo columns are the only recomputation (their loads hit in L2,
+// where the neighbouring tile of the same XCD reads the same lines), plus one
+// warm-up plane on each side of the march.
 //
-// Workgroups are renumbered so that each XCD (hardware dispatch is
-// round-robin over the 8 XCDs) receives a contiguous range of tiles, which
-// keeps the halo columns of neighbouring tiles inside one L2.
+// Addressing.  Populations are stored row-interleaved: the Q values of the X
+// nodes of one row are contiguous, direction-major (dsm_lattice.h).  A wave's
+// row is uniform, so the 9 source rows of a pull are scalar base addresses
+// and the lanes only add their (wrapped) x - 1, x, x + 1.
+//
+// Interpolated bounce-back.  A fluid node x pulls f_i from x - c_i; when that
+// node is solid, the slot holds no population of its own, and the link kernel
+// (dsm_links.hip) has already written the bounce-back value for x into it
+// before this step.  The pull is therefore the same for every link.
 #include <math.h>
 
 #include "dsm_internal.h"
@@ -38,109 +49,85 @@ __device__ __forceinline__ int pmod(int a, int n) {
 
 __device__ __forceinline__ float s_i(float cu, float uu) { return 3.f * cu + 4.5f * cu * cu - 1.5f * uu; }
 
-// Wrapped x-1, x, x+1 and the row offsets X*(y-1, y, y+1) of a column.
-struct Col {
-    int xs[3];
-    int ys[3];
-};
-
-__device__ __forceinline__ Col make_col(int px, int py, int X, int Y) {
-    Col c;
-    c.xs[0] = pmod(px - 1, X);
-    c.xs[1] = pmod(px, X);
-    c.xs[2] = pmod(px + 1, X);
-    c.ys[0] = pmod(py - 1, Y) * X;
-    c.ys[1] = pmod(py, Y) * X;
-    c.ys[2] = pmod(py + 1, Y) * X;
-    return c;
-}
-
-// Plane offsets XY*(z-1, z, z+1), z in [0, Z).
-struct Pl {
-    int zs[3];
-};
-
-__device__ __forceinline__ Pl make_pl(int z, int Z, int XY) {
-    Pl p;
-    p.zs[0] = (z == 0 ? Z - 1 : z - 1) * XY;
-    p.zs[1] = z * XY;
-    p.zs[2] = (z == Z - 1 ? 0 : z + 1) * XY;
-    return p;
-}
-
-// node index of position + s * c_i
-template <int D>
-__device__ __forceinline__ int nidx(const Col& c, const Pl& p, int i, int s) {
-    using L = Lattice<D>;
-    return c.xs[1 + s * L::cx[i]] + c.ys[1 + s * L::cy[i]] + p.zs[1 + s * L::cz[i]];
-}
-
-// Wall fraction of the link along direction k (FP64, boundary links only):
-// distance to the C1 = 1/2 level from the tanh profile, along the link.
-template <int D>
-__device__ double link_fraction(const double gc[3], double gnorm, double xi, int k) {
-    using L = Lattice<D>;
-    if (gnorm < 1e-12) return 0.5;
-    const double len = (L::cx[k] * L::cx[k] + L::cy[k] * L::cy[k] + L::cz[k] * L::cz[k]) == 1
-                           ? 1.0
-                           : 1.4142135623730951;
-    const double cosnc = (gc[0] * L::cx[k] + gc[1] * L::cy[k] + gc[2] * L::cz[k]) / (gnorm * len);
-    if (cosnc <= 1e-6) return 0.5;
-    const double q = xi / cosnc / len;
-    return q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
-}
-
-template <int D, int TX, int TY>
+template <int D, int TXW, int TY>
 struct Tile {
+    static constexpr int TX = 64 * TXW;
     static constexpr int NT = TX * TY;
+    static constexpr int NW = TXW * TY;        // waves
     static constexpr int HY = D == 3 ? 1 : 0;  // halo rows along y (none in 2D)
     static constexpr int CRX = TX + 2;
     static constexpr int CRY = TY + 2 * HY;
     static constexpr int CR = CRX * CRY;
-    static constexpr int NHALO = CR - NT;
-    static constexpr int NA = 1 + (NHALO + NT - 1) / NT;  // C positions per thread
+    // Halo of the C region: waves 0 .. NROWH-1 take the rows above and below
+    // the tile (top: waves 0 .. TXW-1, bottom: TXW .. 2 TXW-1), over the same
+    // columns as their own row segment; wave SIDE takes the NSIDE remaining
+    // columns (the four corners, then the left and right end of each row).
+    static constexpr int NROWH = 2 * HY * TXW;
+    static constexpr int SIDE = NROWH;
+    static constexpr int NSIDE = 4 * HY + 2 * TY;
+    static_assert(SIDE < NW && NSIDE <= 64, "tile too small for its halo");
 
-    // C-region coordinates of the k-th position (k < NT: interior column k)
-    static __device__ __forceinline__ void cpos(int k, int& rx, int& ry) {
-        if (k < NT) {
-            rx = (k % TX) + 1;
-            ry = (k / TX) + HY;
+    static __device__ __forceinline__ void side_pos(int s, int& rx, int& ry) {
+        if (HY && s < 4) {
+            rx = (s & 1) ? CRX - 1 : 0;
+            ry = (s & 2) ? CRY - 1 : 0;
             return;
         }
-        int h = k - NT;
-        if (h < HY * CRX) {
-            rx = h % CRX;
-            ry = h / CRX;
-            return;
-        }
-        h -= HY * CRX;
-        if (h < HY * CRX) {
-            rx = h % CRX;
-            ry = HY + TY + h / CRX;
-            return;
-        }
-        h -= HY * CRX;
-        ry = HY + h / 2;
-        rx = (h % 2) ? TX + 1 : 0;
+        s -= 4 * HY;
+        ry = HY + (s >> 1);
+        rx = (s & 1) ? CRX - 1 : 0;
     }
 };
 
-template <int D, int TX, int TY, int STAGE, bool PULL>
-__global__ void __launch_bounds__(TX* TY)
+
+// Occupancy request for the fused kernel (none by default).
+#ifdef DSM_FUSED_WPE
+#define DSM_WAVES_PER_EU __attribute__((amdgpu_waves_per_eu(DSM_FUSED_WPE, 8)))
+#else
+#define DSM_WAVES_PER_EU
+#endif
+
+// Buffer resources.  Every plane of populations gets a descriptor (base =
+// start of the plane, range = one plane), so the hot loads and stores address
+// with a scalar offset (row and direction, uniform per wave) plus a 32-bit
+// lane offset (x), and an access outside the plane returns 0 / is dropped
+// instead of faulting.  Word 3 is the gfx9 raw-buffer format.
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kNonTemporal = 2;  // cache-policy bit of buffer stores: nt
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, long long plane_floats, int z) {
+    // the plane start is wave-uniform; saying so keeps the descriptor in SGPRs
+    const unsigned long long a = (unsigned long long)(base + plane_floats * z);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    float* p = reinterpret_cast<float*>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(plane_floats * 4), kRsrcWord3);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNonTemporal);
+}
+
+template <int D, int TXW, int TY, int STAGE, bool PULL>
+__global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
     k_step_fused(Geom g, Phys ph, const float* __restrict__ fsrc, const float* __restrict__ gsrc,
                  float* __restrict__ fdst, float* __restrict__ gdst, const float* __restrict__ c1g,
                  const uint8_t* __restrict__ mask, int* __restrict__ flag, int TZ, int ntx, int nty) {
-    using T = Tile<D, TX, TY>;
+    using T = Tile<D, TXW, TY>;
     using L = Lattice<D>;
     constexpr int Q = L::Q;
-    constexpr int NT = T::NT, CRX = T::CRX, CR = T::CR, HY = T::HY;
-    __shared__ float s_c[4][CR];                       // C of planes l-3..l (ring)
-    __shared__ float s_c1[STAGE == 2 ? 4 : 1][CR];     // frozen C1, same ring
+    constexpr int TX = T::TX, CRX = T::CRX, CR = T::CR, HY = T::HY;
+    __shared__ float s_c[4][CR];                                    // C of planes l-3..l (ring)
+    __shared__ float s_c1[STAGE == 2 ? 4 : 1][STAGE == 2 ? CR : 1];  // frozen C1, same ring
 
-    const int X = g.X, Y = g.Y, Z = g.Z, XY = X * Y;
-    const long long N = g.N;
+    const int X = g.X, Y = g.Y, Z = g.Z;
+    const int QX = Q * X;                          // floats per row of populations
+    const long long PL = (long long)QX * Y;        // floats per plane of populations
 
-    // XCD-aware tile order: XCD k (= blockIdx % 8) gets a contiguous range
+    // XCD-aware tile order: hardware dispatch is round-robin over the 8 XCDs,
+    // so XCD k (= blockIdx % 8) is given a contiguous range of tiles
     const int nb = gridDim.x, b = blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
     const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
@@ -150,209 +137,192 @@ __global__ void __launch_bounds__(TX* TY)
     const int zlen = min(TZ, Z - z0);
 
     const int t = threadIdx.x;
-    const int tx = t % TX, ty = t / TX;
-    const bool active = (x0 + tx < X) && (y0 + ty < Y);
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index (uniform)
+    const int lane = t & 63;
+    const int xseg = wv % TXW, yrow = wv / TXW;
+    const int x = x0 + xseg * 64 + lane;
+    const int y = y0 + yrow;  // uniform
+    const bool active = (x < X) && (y < Y);
+    const int rint = (1 + xseg * 64 + lane) + CRX * (HY + yrow);  // own region index
 
-    // C positions of this thread: its own column, then halo columns
-    Col ca[T::NA];
-    int ra[T::NA];
-    bool va[T::NA];
-#pragma unroll
-    for (int k = 0; k < T::NA; ++k) {
-        const int pk = k == 0 ? t : NT + (k - 1) * NT + t;
-        va[k] = pk < CR;
-        int rx = 0, ry = 0;
-        if (va[k]) T::cpos(pk, rx, ry);
-        ra[k] = rx + CRX * ry;
-        ca[k] = make_col(x0 - 1 + rx, y0 - HY + ry, X, Y);
-    }
-    const int rint = ra[0];
+    // Own column, wrapped (lanes beyond the lattice edge of a ragged tile
+    // compute C of the wrapped column: the last real column needs it).
+    const int xv[3] = {pmod(x - 1, X), pmod(x, X), pmod(x + 1, X)};   // x-1, x, x+1
+    const unsigned xb[3] = {4u * xv[0], 4u * xv[1], 4u * xv[2]};         // as byte offsets
+    const int yw = pmod(y, Y);
+    const int yv[3] = {yw == 0 ? Y - 1 : yw - 1, yw, yw + 1 == Y ? 0 : yw + 1};
+
+    // Halo columns of this wave (see Tile)
+    const bool row_halo = wv < T::NROWH;  // uniform
+    const int hbot = HY ? (wv / TXW) : 0;  // 0: row above the tile, 1: row below
+    const int hyw = pmod(hbot ? y0 + TY : y0 - 1, Y);
+    const int hyv[3] = {hyw == 0 ? Y - 1 : hyw - 1, hyw, hyw + 1 == Y ? 0 : hyw + 1};
+    const int hreg = (1 + xseg * 64 + lane) + CRX * (hbot ? T::CRY - 1 : 0);
+    const bool side = wv == T::SIDE && lane < T::NSIDE;
+    int srx = 0, sry = 0;
+    if (side) T::side_pos(lane, srx, sry);
+    const int sreg = srx + CRX * sry;
+    const int sxw = pmod(x0 - 1 + srx, X), syw = pmod(y0 - HY + sry, Y);
+    const int sxv[3] = {sxw == 0 ? X - 1 : sxw - 1, sxw, sxw + 1 == X ? 0 : sxw + 1};
+    const int syv[3] = {syw == 0 ? Y - 1 : syw - 1, syw, syw + 1 == Y ? 0 : syw + 1};
 
     const float fpref3 = 3.f * ph.fpref;
     const float k13 = ph.k1 + ph.k3;
     float gA[Q], gB[Q];
 
-    // Iteration j: lead plane l = z0 - 1 + j goes into ring slot j & 3; the
-    // plane c = l - 1 (slot (j+3)&3, neighbours (j+2)&3 and j&3) collides.
     auto iteration = [&](int j, float (&gload)[Q], float (&gcoll)[Q]) {
-        const int l = z0 - 1 + j;
-        // ---- A -----------------------------------------------------------
+        const int l = z0 - 1 + j;  // lead plane
+        const int c = l - 1;       // collision plane (valid when j >= 2)
+        const int lz = pmod(l, Z);
+        const int zl[3] = {lz == 0 ? Z - 1 : lz - 1, lz, lz + 1 == Z ? 0 : lz + 1};
+        const int sl = j & 3;
+        const bool collide = j >= 2 && active;
+        const int cz = j >= 2 ? c : 0;  // c is inside [0, Z) from j = 2 on (uniform)
+        const int zc[3] = {cz == 0 ? Z - 1 : cz - 1, cz, cz + 1 == Z ? 0 : cz + 1};
+
+        // ---- phase 1 --------------------------------------------------------
+        const __amdgpu_buffer_rsrc_t gl[3] = {plane_rsrc(gsrc, PL, zl[0]), plane_rsrc(gsrc, PL, zl[1]),
+                                              plane_rsrc(gsrc, PL, zl[2])};
+        // lead plane, own column: pulled g and their sum
         {
-            const Pl pl = make_pl(pmod(l, Z), Z, XY);
-            const int sl = j & 3;
+            float acc = 0.f;
 #pragma unroll
-            for (int k = 0; k < T::NA; ++k) {
-                if (!va[k]) continue;
-                float acc = 0.f;
-                if (k == 0) {
+            for (int i = 0; i < Q; ++i) {
+                const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+                gload[i] = bload(gl[sz], xb[sx], 4u * (unsigned)(yv[sy] * QX + i * X));
+            }
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        const int src = PULL ? nidx<D>(ca[0], pl, i, -1) : (ca[0].xs[1] + ca[0].ys[1] + pl.zs[1]);
-                        gload[i] = gsrc[(size_t)i * N + src];
-                    }
+            for (int i = 0; i < Q; ++i) acc += gload[i];
+            s_c[sl][rint] = acc;
+            if (STAGE == 2) s_c1[sl][rint] = c1g[xv[1] + X * ((long long)yv[1] + (long long)Y * lz)];
+        }
+        // lead plane, halo columns (same summation order as the own column)
+        if (row_halo) {
+            float h[Q], acc = 0.f;
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) acc += gload[i];
-                } else {
-                    float tmp[Q];
+            for (int i = 0; i < Q; ++i) {
+                const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+                h[i] = bload(gl[sz], xb[sx], 4u * (unsigned)(hyv[sy] * QX + i * X));
+            }
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        const int src = PULL ? nidx<D>(ca[k], pl, i, -1) : (ca[k].xs[1] + ca[k].ys[1] + pl.zs[1]);
-                        tmp[i] = gsrc[(size_t)i * N + src];
-                    }
+            for (int i = 0; i < Q; ++i) acc += h[i];
+            s_c[sl][hreg] = acc;
+            if (STAGE == 2) s_c1[sl][hreg] = c1g[xv[1] + X * ((long long)hyw + (long long)Y * lz)];
+        } else if (side) {
+            float h[Q], acc = 0.f;
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) acc += tmp[i];
-                }
-                s_c[sl][ra[k]] = acc;
-                if (STAGE == 2) s_c1[sl][ra[k]] = c1g[ca[k].xs[1] + ca[k].ys[1] + pl.zs[1]];
+            for (int i = 0; i < Q; ++i) {
+                const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+                h[i] = bload(gl[sz], 4u * (unsigned)(syv[sy] * QX + i * X + sxv[sx]), 0u);
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) acc += h[i];
+            s_c[sl][sreg] = acc;
+            if (STAGE == 2) s_c1[sl][sreg] = c1g[sxw + X * ((long long)syw + (long long)Y * lz)];
+        }
+        // collision plane: f (in flight across the barrier)
+        bool solid = false;
+        if (STAGE == 2 && collide) solid = s_c1[(j + 3) & 3][rint] > 0.5f;
+        float f[Q];
+        if (collide && !solid) {
+            const __amdgpu_buffer_rsrc_t fc[3] = {plane_rsrc(fsrc, PL, zc[0]), plane_rsrc(fsrc, PL, zc[1]),
+                                                  plane_rsrc(fsrc, PL, zc[2])};
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+                f[i] = bload(fc[sz], xb[sx], 4u * (unsigned)(yv[sy] * QX + i * X));
             }
         }
         __syncthreads();
-        // ---- C: plane c = l - 1 ------------------------------------------
-        if (j >= 2 && active) {
-            const int c = l - 1;  // inside [z0, z0 + zlen)
-            const Pl pc = make_pl(c, Z, XY);
-            const int sm_ = (j + 2) & 3, s0 = (j + 3) & 3, sp = j & 3;  // planes c-1, c, c+1
-            const int self = ca[0].xs[1] + ca[0].ys[1] + pc.zs[1];
-            const float C = s_c[s0][rint];
-            // Laplacians and gradient of C; Laplacian of C1
-            float lc = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+
+        // ---- phase 2: collide plane c --------------------------------------
+        if (!collide) return;
+        const int sm_ = (j + 2) & 3, s0 = (j + 3) & 3, sp = j & 3;  // planes c-1, c, c+1
+        const float C = s_c[s0][rint];
+        // Laplacian and gradient of C (pairs of opposite directions)
+        float lc = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);  // plane of x + c_i
+            const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);  // plane of x - c_i
+            const int o = L::cx[i] + CRX * L::cy[i];
+            const float a = s_c[spl][rint + o], bm = s_c[smi][rint - o];
+            lc += L::w[i] * ((a - C) + (bm - C));
+            const float d = a - bm;
+            gx += L::w[i] * L::cx[i] * d;
+            gy += L::w[i] * L::cy[i] * d;
+            gz += L::w[i] * L::cz[i] * d;
+        }
+        lc *= 6.f;
+        float mu, C1 = 0.f;
+        if (STAGE == 2) {
+            C1 = s_c1[s0][rint];
+            float l1 = 0.f;
 #pragma unroll
             for (int i = 1; i < Q; i += 2) {
-                const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);  // plane of x + c_i
-                const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);  // plane of x - c_i
+                const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);
+                const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);
                 const int o = L::cx[i] + CRX * L::cy[i];
-                const float a = s_c[spl][rint + o], bm = s_c[smi][rint - o];
-                lc += L::w[i] * ((a - C) + (bm - C));
-                const float d = a - bm;
-                gx += L::w[i] * L::cx[i] * d;
-                gy += L::w[i] * L::cy[i] * d;
-                gz += L::w[i] * L::cz[i] * d;
+                l1 += L::w[i] * ((s_c1[spl][rint + o] - C1) + (s_c1[smi][rint - o] - C1));
             }
-            lc *= 6.f;
-            float mu, C1 = 0.f;
-            if (STAGE == 2) {
-                C1 = s_c1[s0][rint];
-                float l1 = 0.f;
-#pragma unroll
-                for (int i = 1; i < Q; i += 2) {
-                    const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);
-                    const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);
-                    const int o = L::cx[i] + CRX * L::cy[i];
-                    l1 += L::w[i] * ((s_c1[spl][rint + o] - C1) + (s_c1[smi][rint - o] - C1));
-                }
-                l1 *= 6.f;
-                const float S = C1 + C;
-                mu = ph.k2 * C * (1.f - C) * (1.f - 2.f * C) + ph.k3 * S * (1.f - S) * (1.f - 2.f * S) -
-                     ph.a2 * ph.k2 * lc - ph.a2 * ph.k3 * (l1 + lc);
-            } else {
-                mu = k13 * C * (1.f - C) * (1.f - 2.f * C);
-                const bool inS = mask[self] != 0;
-                if ((C < 0.5f && inS) || (C > 0.5f && !inS)) mu += 2.f * ph.beta * (C - 0.5f);
-                mu -= ph.a2 * k13 * lc;
-                if (C < 0.f) mu += 2.f * ph.omega * C;
-                if (C > 1.f) mu -= 2.f * ph.omega * (1.f - C);
-            }
-            const bool solid = STAGE == 2 && C1 > 0.5f;
-            float ux = 0.f, uy = 0.f, uz = 0.f, pt = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
-            float f[Q];
-            if (!solid) {
-                Fx = mu * 3.f * gx;
-                Fy = mu * 3.f * gy;
-                Fz = mu * 3.f * gz;
-                if (STAGE == 2) {
-                    Fx += C * ph.grav[0];
-                    Fy += C * ph.grav[1];
-                    Fz += C * ph.grav[2];
-                }
-                // pull f; links whose upstream node is solid are rebuilt below
-                unsigned cut = 0;
-                if (STAGE == 2 && PULL) {
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const int su = L::cz[i] > 0 ? sm_ : (L::cz[i] < 0 ? sp : s0);
-                        if (s_c1[su][rint - L::cx[i] - CRX * L::cy[i]] > 0.5f) cut |= 1u << i;
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const int src = PULL ? nidx<D>(ca[0], pc, i, -1) : self;
-                    f[i] = ((cut >> i) & 1u) ? 0.f : fsrc[(size_t)i * N + src];
-                }
-                if (cut) {
-                    double gc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const int sl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);
-                        const double v = (double)s_c1[sl][rint + L::cx[i] + CRX * L::cy[i]];
-                        const double wi = (L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i]) == 1
-                                              ? (D == 2 ? 1.0 / 9.0 : 1.0 / 18.0)
-                                              : 1.0 / 36.0;
-                        gc[0] += wi * L::cx[i] * v;
-                        gc[1] += wi * L::cy[i] * v;
-                        gc[2] += wi * L::cz[i] * v;
-                    }
-                    gc[0] *= 3.0;
-                    gc[1] *= 3.0;
-                    gc[2] *= 3.0;
-                    const double gn = sqrt(gc[0] * gc[0] + gc[1] * gc[1] + gc[2] * gc[2]);
-                    double tt = 1.0 - 2.0 * (double)C1;
-                    tt = tt < 0.0 ? 0.0 : (tt > 1.0 - 1e-12 ? 1.0 - 1e-12 : tt);
-                    const double xi = 2.0 * (double)ph.alpha * atanh(tt);
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        if (!((cut >> i) & 1u)) continue;
-                        const int k = opp(i);
-                        double q = link_fraction<D>(gc, gn, xi, k);
-                        const int sd = L::cz[i] > 0 ? sp : (L::cz[i] < 0 ? sm_ : s0);
-                        const bool down_solid = s_c1[sd][rint + L::cx[i] + CRX * L::cy[i]] > 0.5f;
-                        const double fk = (double)fsrc[(size_t)k * N + self];
-                        double v;
-                        if (q < 0.5 && !down_solid) {
-                            const int dn = nidx<D>(ca[0], pc, i, +1);
-                            v = 2.0 * q * fk + (1.0 - 2.0 * q) * (double)fsrc[(size_t)k * N + dn];
-                        } else {
-                            if (q < 0.5) q = 0.5;
-                            v = fk / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * (double)fsrc[(size_t)i * N + self];
-                        }
-                        f[i] = (float)v;
-                    }
-                }
-                float mx = 0.f, my = 0.f, mz = 0.f;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    pt += f[i];
-                    mx += L::cx[i] * f[i];
-                    my += L::cy[i] * f[i];
-                    mz += L::cz[i] * f[i];
-                }
-                ux = mx + 0.5f * Fx;
-                uy = my + 0.5f * Fy;
-                uz = mz + 0.5f * Fz;
-            }
-            const float uu = ux * ux + uy * uy + uz * uz;
-            if (solid) {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) fdst[(size_t)i * N + self] = 0.f;
-            } else {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
-                    const float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
-                    const float feq = L::w[i] * (pt + s_i(cu, uu));
-                    fdst[(size_t)i * N + self] = f[i] - (f[i] - feq) * ph.inv_tau + fpref3 * L::w[i] * cF;
-                }
-            }
-            float restg = C;
-#pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
-                const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
-                restg -= geq;
-                gdst[(size_t)i * N + self] = gcoll[i] - (gcoll[i] - geq) * ph.inv_taug;
-            }
-            gdst[self] = gcoll[0] - (gcoll[0] - restg) * ph.inv_taug;
-            if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
+            l1 *= 6.f;
+            const float S = C1 + C;
+            mu = ph.k2 * C * (1.f - C) * (1.f - 2.f * C) + ph.k3 * S * (1.f - S) * (1.f - 2.f * S) -
+                 ph.a2 * ph.k2 * lc - ph.a2 * ph.k3 * (l1 + lc);
+        } else {
+            mu = k13 * C * (1.f - C) * (1.f - 2.f * C);
+            const bool inS = mask[xv[1] + X * ((long long)yv[1] + (long long)Y * c)] != 0;
+            if ((C < 0.5f && inS) || (C > 0.5f && !inS)) mu += 2.f * ph.beta * (C - 0.5f);
+            mu -= ph.a2 * k13 * lc;
+            if (C < 0.f) mu += 2.f * ph.omega * C;
+            if (C > 1.f) mu -= 2.f * ph.omega * (1.f - C);
         }
+        float ux = 0.f, uy = 0.f, uz = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f, pt = 0.f;
+        if (!solid) {
+            Fx = mu * 3.f * gx;
+            Fy = mu * 3.f * gy;
+            Fz = mu * 3.f * gz;
+            if (STAGE == 2) {
+                Fx += C * ph.grav[0];
+                Fy += C * ph.grav[1];
+                Fz += C * ph.grav[2];
+            }
+            float mx = 0.f, my = 0.f, mz = 0.f;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                pt += f[i];
+                mx += L::cx[i] * f[i];
+                my += L::cy[i] * f[i];
+                mz += L::cz[i] * f[i];
+            }
+            ux = mx + 0.5f * Fx;
+            uy = my + 0.5f * Fy;
+            uz = mz + 0.5f * Fz;
+        }
+        const float uu = ux * ux + uy * uy + uz * uz;
+        const unsigned own_off = 4u * (unsigned)(yv[1] * QX);
+        if (!solid) {
+            const __amdgpu_buffer_rsrc_t fo = plane_rsrc(fdst, PL, c);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
+                const float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
+                const float feq = L::w[i] * (pt + s_i(cu, uu));
+                bstore_nt(fo, xb[1], own_off + 4u * (unsigned)(i * X),
+                          f[i] - (f[i] - feq) * ph.inv_tau + fpref3 * L::w[i] * cF);
+            }
+        }
+        const __amdgpu_buffer_rsrc_t go = plane_rsrc(gdst, PL, c);
+        float restg = C;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
+            const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
+            restg -= geq;
+            bstore_nt(go, xb[1], own_off + 4u * (unsigned)(i * X), gcoll[i] - (gcoll[i] - geq) * ph.inv_taug);
+        }
+        bstore_nt(go, xb[1], own_off, gcoll[0] - (gcoll[0] - restg) * ph.inv_taug);
+        if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
     };
 
     const int J = zlen + 2;
@@ -362,33 +332,35 @@ __global__ void __launch_bounds__(TX* TY)
     }
 }
 
-template <int D, int TX, int TY, int STAGE, bool PULL>
+template <int D, int TXW, int TY, int STAGE, bool PULL>
 hipError_t launch_cfg(const Geom& g, const Phys& ph, const float* fsrc, const float* gsrc, float* fdst,
                       float* gdst, const float* c1, const uint8_t* mask, int* flag, int TZ, hipStream_t st) {
+    constexpr int TX = 64 * TXW;
     const int ntx = (g.X + TX - 1) / TX;
     const int nty = (g.Y + TY - 1) / TY;
     const int ntz = (g.Z + TZ - 1) / TZ;
     const long long nblocks = (long long)ntx * nty * ntz;
-    hipLaunchKernelGGL((k_step_fused<D, TX, TY, STAGE, PULL>), dim3((unsigned)nblocks), dim3(TX * TY), 0, st, g,
-                       ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, ntx, nty);
+    if (nblocks < 1 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_step_fused<D, TXW, TY, STAGE, PULL>), dim3((unsigned)nblocks), dim3(64 * TXW * TY), 0,
+                       st, g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, ntx, nty);
     return hipGetLastError();
 }
 
-template <int D, int TX, int TY>
+template <int D, int TXW, int TY>
 hipError_t launch_tile(const Geom& g, const Phys& ph, const float* fsrc, const float* gsrc, float* fdst,
                        float* gdst, const float* c1, const uint8_t* mask, int pull, int* flag, int TZ,
                        hipStream_t st) {
     if (ph.stage == 2) {
-        if (pull) return launch_cfg<D, TX, TY, 2, true>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
-        return launch_cfg<D, TX, TY, 2, false>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
+        if (pull) return launch_cfg<D, TXW, TY, 2, true>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
+        return launch_cfg<D, TXW, TY, 2, false>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
     }
-    if (pull) return launch_cfg<D, TX, TY, 1, true>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
-    return launch_cfg<D, TX, TY, 1, false>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
+    if (pull) return launch_cfg<D, TXW, TY, 1, true>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
+    return launch_cfg<D, TXW, TY, 1, false>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
 }
 
 }  // namespace
 
-int fused_tile_variants(int dim) { return dim == 2 ? 3 : 4; }
+int fused_tile_variants(int dim) { return 3; }
 
 hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, const float* fsrc, const float* gsrc,
                              float* fdst, float* gdst, const float* c1, const uint8_t* mask, int pull, int* flag,
@@ -396,16 +368,15 @@ hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, const float
     if (TZ < 1) TZ = 1;
     if (dim == 2) {
         switch (variant) {
-            case 1: return launch_tile<2, 256, 1>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
-            case 2: return launch_tile<2, 64, 1>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
-            default: return launch_tile<2, 128, 1>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
+            case 1: return launch_tile<2, 2, 1>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
+            case 2: return launch_tile<2, 1, 1>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
+            default: return launch_tile<2, 4, 1>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
         }
     }
     switch (variant) {
-        case 1: return launch_tile<3, 64, 4>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
-        case 2: return launch_tile<3, 64, 8>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
-        case 3: return launch_tile<3, 32, 16>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
-        default: return launch_tile<3, 32, 8>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
+        case 1: return launch_tile<3, 1, 8>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
+        case 2: return launch_tile<3, 2, 4>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
+        default: return launch_tile<3, 1, 4>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
     }
 }
 

@@ -21,6 +21,14 @@ enum {
     RED_SLOTS = 8
 };
 constexpr int kReduceBlocks = 1024;  // partial sums per reduction (fixed order)
+constexpr int kLinksPerNode = 2;     // capacity of the cut-link table, per lattice node
+
+// One cut link of the fluid stage: f[dst] = ca f[a] + cb f[b] (population
+// indices in the device layout).
+struct LinkRec {
+    unsigned dst, a, b;
+    float ca, cb;
+};
 
 // Device arrays of one simulation, carved from the caller's buffer.
 struct DevArrays {
@@ -34,6 +42,9 @@ struct DevArrays {
     double* partials; // [kReduceBlocks][RED_SLOTS]
     double* red;      // [RED_SLOTS]
     int* flag;        // [4] non-finite flag of the step kernels
+    int2* ent;        // [N] boundary nodes of the fluid stage: (node, mask of cut links)
+    LinkRec* links;   // [kLinksPerNode * N] cut links as two-term records
+    int* nlinks;      // [2] number of entries, number of records
 };
 
 // --- launchers (dsm_kernels.hip) -------------------------------------------
@@ -61,10 +72,21 @@ hipError_t launch_reduce(int dim, const Geom& g, const Phys& ph, const float* c1
                          const uint8_t* mask, const float* aux, double* partials, double* red,
                          hipStream_t st);
 
+// --- interpolated bounce-back (dsm_links.hip) ------------------------------
+// find: lists the fluid nodes with cut links (C1 fixed), count[0] entries;
+// build: one record per cut link, count[1] records; bounce: writes the rebuilt
+// populations into the solid slots they are pulled from, in the
+// post-collision buffer f.
+hipError_t launch_find_links(int dim, const Geom& g, const float* c1, int2* ent, int* count, hipStream_t st);
+hipError_t launch_build_links(int dim, const Geom& g, double alpha, const float* c1, const int2* ent, int nent,
+                              LinkRec* rec, long long cap, int* count, hipStream_t st);
+hipError_t launch_bounce(float* f, const LinkRec* rec, int count, hipStream_t st);
+
 // --- fused step (dsm_fused.hip) ---------------------------------------------
-// variant selects the workgroup tile (3D: 0 = 32x8, 1 = 64x4, 2 = 64x8,
-// 3 = 32x16 columns; 2D: 0 = 128, 1 = 256, 2 = 64 columns); TZ is the number
-// of planes each workgroup marches through.
+// variant selects the workgroup tile (3D: 0 = 64x4, 1 = 64x8, 2 = 128x4
+// columns; 2D: 0 = 256, 1 = 128, 2 = 64 columns); TZ is the number of planes
+// each workgroup marches through.  In the fluid stage with pull != 0 the
+// bounce-back slots of fsrc must have been written by launch_bounce.
 int fused_tile_variants(int dim);
 hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, const float* fsrc,
                              const float* gsrc, float* fdst, float* gdst, const float* c1,

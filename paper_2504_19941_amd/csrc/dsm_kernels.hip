@@ -86,7 +86,6 @@ template <int D>
 __device__ void pull_f(const Geom& g, const float* fsrc, const float* c1, float alpha, int x, int y,
                        int z, long long n, float fout[Lattice<D>::Q]) {
     using L = Lattice<D>;
-    const long long N = g.N;
     unsigned cut = 0;
     long long up[L::Q];
 #pragma unroll
@@ -96,7 +95,7 @@ __device__ void pull_f(const Geom& g, const float* fsrc, const float* c1, float 
     }
     if (!cut) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) fout[i] = fsrc[(long long)i * N + up[i]];
+        for (int i = 0; i < L::Q; ++i) fout[i] = fsrc[pop_index(g, L::Q, i, up[i])];
         return;
     }
     double gc[3] = {0.0, 0.0, 0.0};
@@ -119,20 +118,20 @@ __device__ void pull_f(const Geom& g, const float* fsrc, const float* c1, float 
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         if (!((cut >> i) & 1u)) {
-            fout[i] = fsrc[(long long)i * N + up[i]];
+            fout[i] = fsrc[pop_index(g, L::Q, i, up[i])];
             continue;
         }
         const int k = opp(i);
         double q = link_fraction<D>(gc, gnorm, xi, k);
         long long dn = shifted<D>(g, x, y, z, i, +1);
         bool down_solid = c1[dn] > 0.5f;
-        double fk = (double)fsrc[(long long)k * N + n];
+        double fk = (double)fsrc[pop_index(g, L::Q, k, n)];
         double v;
         if (q < 0.5 && !down_solid) {
-            v = 2.0 * q * fk + (1.0 - 2.0 * q) * (double)fsrc[(long long)k * N + dn];
+            v = 2.0 * q * fk + (1.0 - 2.0 * q) * (double)fsrc[pop_index(g, L::Q, k, dn)];
         } else {
             if (q < 0.5) q = 0.5;
-            v = fk / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * (double)fsrc[(long long)i * N + n];
+            v = fk / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * (double)fsrc[pop_index(g, L::Q, i, n)];
         }
         fout[i] = (float)v;
     }
@@ -167,7 +166,7 @@ __global__ void k_moment(Geom g, const float* __restrict__ gsrc, float* __restri
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
-        acc += gsrc[(long long)i * g.N + src];
+        acc += gsrc[pop_index(g, L::Q, i, src)];
     }
     phi[n] = acc;
 }
@@ -240,11 +239,11 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
                 pull_f<D>(g, fsrc, c1, ph.alpha, x, y, z, n, f);
             } else {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) f[i] = fsrc[(long long)i * N + shifted<D>(g, x, y, z, i, -1)];
+                for (int i = 0; i < Q; ++i) f[i] = fsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) f[i] = fsrc[(long long)i * N + n];
+            for (int i = 0; i < Q; ++i) f[i] = fsrc[pop_index(g, L::Q, i, n)];
         }
         float mx = 0.f, my = 0.f, mz = 0.f;
 #pragma unroll
@@ -273,7 +272,7 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
     const float uu = ux * ux + uy * uy + uz * uz;
     if (solid) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) fdst[(long long)i * N + n] = 0.f;
+        for (int i = 0; i < Q; ++i) fdst[pop_index(g, L::Q, i, n)] = 0.f;
     } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -281,7 +280,7 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
             float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
             float feq = L::w[i] * (pt + s_i(cu, uu));
             float Fi = ph.fpref * L::w[i] * 3.f * cF;
-            fdst[(long long)i * N + n] = f[i] - (f[i] - feq) * ph.inv_tau + Fi;
+            fdst[pop_index(g, L::Q, i, n)] = f[i] - (f[i] - feq) * ph.inv_tau + Fi;
         }
     }
     const float m = mu[n];
@@ -290,16 +289,16 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
-        gi[i] = gsrc[(long long)i * N + src];
+        gi[i] = gsrc[pop_index(g, L::Q, i, src)];
     }
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
         float geq = L::w[i] * m + L::w[i] * C * s_i(cu, uu);
         rest -= geq;
-        gdst[(long long)i * N + n] = gi[i] - (gi[i] - geq) * ph.inv_taug;
+        gdst[pop_index(g, L::Q, i, n)] = gi[i] - (gi[i] - geq) * ph.inv_taug;
     }
-    gdst[n] = gi[0] - (gi[0] - rest) * ph.inv_taug;
+    gdst[pop_index(g, L::Q, 0, n)] = gi[0] - (gi[0] - rest) * ph.inv_taug;
     if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
 }
 
@@ -310,17 +309,16 @@ __global__ void k_init_populations(Geom g, const float* __restrict__ phi, const 
     using L = Lattice<D>;
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
-    const long long N = g.N;
     float C = phi[n], m = mu[n], rest = C;
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         float geq = L::w[i] * m;
         rest -= geq;
-        gdst[(long long)i * N + n] = geq;
-        fdst[(long long)i * N + n] = 0.f;
+        gdst[pop_index(g, L::Q, i, n)] = geq;
+        fdst[pop_index(g, L::Q, i, n)] = 0.f;
     }
-    gdst[n] = rest;
-    fdst[n] = 0.f;
+    gdst[pop_index(g, L::Q, 0, n)] = rest;
+    fdst[pop_index(g, L::Q, 0, n)] = 0.f;
 }
 
 // post-collision -> post-stream (with bounce-back for f in the fluid stage)
@@ -331,11 +329,10 @@ __global__ void k_pull_state(Geom g, Phys ph, const float* __restrict__ fsrc, co
     constexpr int Q = L::Q;
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
-    const long long N = g.N;
     int x, y, z;
     decode(g, n, x, y, z);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gdst[(long long)i * N + n] = gsrc[(long long)i * N + shifted<D>(g, x, y, z, i, -1)];
+    for (int i = 0; i < Q; ++i) gdst[pop_index(g, L::Q, i, n)] = gsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
     const bool solid = ph.stage == 2 && c1[n] > 0.5f;
     float f[Q];
     if (solid) {
@@ -345,10 +342,10 @@ __global__ void k_pull_state(Geom g, Phys ph, const float* __restrict__ fsrc, co
         pull_f<D>(g, fsrc, c1, ph.alpha, x, y, z, n, f);
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = fsrc[(long long)i * N + shifted<D>(g, x, y, z, i, -1)];
+        for (int i = 0; i < Q; ++i) f[i] = fsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fdst[(long long)i * N + n] = f[i];
+    for (int i = 0; i < Q; ++i) fdst[pop_index(g, L::Q, i, n)] = f[i];
 }
 
 // --- FP64 reductions -------------------------------------------------------

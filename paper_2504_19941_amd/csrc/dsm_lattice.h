@@ -69,4 +69,14 @@ __device__ __forceinline__ long long node_index(const Geom& g, int x, int y, int
     return (long long)x + (long long)g.X * ((long long)y + (long long)g.Y * (long long)z);
 }
 
+// Population layout in HBM, "row-interleaved": the Q populations of the X
+// nodes of one lattice row (fixed stored y and z) are contiguous and
+// direction-major, so population i of node n = x + X*row lives at
+// (row*Q + i)*X + x.  A wave reading one direction of one row segment then
+// touches one contiguous run, and a node's Q values sit within Q*X floats.
+__host__ __device__ __forceinline__ long long pop_index(const Geom& g, int Q, int i, long long n) {
+    const long long row = n / g.X;
+    return (row * Q + i) * g.X + (n - row * g.X);
+}
+
 }  // namespace dsm
