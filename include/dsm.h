@@ -131,6 +131,13 @@ int dsm_set_gravity(dsm_sim* s, const double g[3]);
  * (stability check failed; the state is left as computed), DSM_EDEVICE. */
 int dsm_step(dsm_sim* s, int n);
 
+/* dsm_step with HIP events recorded around every launch (synchronises at the
+ * end): the mean duration, in ms, of the fused step kernel and of the
+ * bounce-back link kernel that precedes it.  For measurement; the events add
+ * a little time between launches.  Fused kernel only.  Errors: DSM_EINVAL,
+ * DSM_ESTATE, DSM_EUNSTABLE, DSM_EDEVICE. */
+int dsm_step_timed(dsm_sim* s, int n, double* step_ms, double* links_ms);
+
 /* Discrete free energy of the current state (FP64 reduction; synchronises):
  * fluid stage, the frozen-solid functional of Sec. II.B without its constant
  * C1 terms; solid stage, the solid-relaxation functional.  Square gradients

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dsm.h"
+#include "dsm.h"
 #include "dsm_internal.h"
 
 using namespace dsm;
@@ -429,6 +429,62 @@ int dsm_step(dsm_sim* s, int n) {
         }
     }
     return DSM_OK;
+}
+
+int dsm_step_timed(dsm_sim* s, int n, double* step_ms, double* links_ms) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (n < 1) return fail(DSM_EINVAL, "n must be >= 1");
+    if (s->stage != 2) return fail(DSM_ESTATE, "dsm_step_timed needs a liquid (dsm_set_liquid) first");
+    if (s->p.kernel != DSM_KERNEL_FUSED) return fail(DSM_EINVAL, "dsm_step_timed times the fused kernel only");
+    std::vector<hipEvent_t> ev((size_t)4 * n, nullptr);
+    auto destroy = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto& e : ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            destroy();
+            return fail(DSM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(r));
+        }
+    }
+    int rc = DSM_OK;
+    for (int t = 0; t < n && !rc; ++t) {
+        const Phys ph = make_phys(s, s->stage);
+        const int c = s->cur, o = 1 - s->cur;
+        hipError_t r = hipEventRecord(ev[4 * t], s->stream);
+        if (r == hipSuccess && s->pull) r = launch_bounce(s->d.f[c], s->d.links, s->nlinks, s->stream);
+        if (r == hipSuccess) r = hipEventRecord(ev[4 * t + 1], s->stream);
+        if (r == hipSuccess) r = hipEventRecord(ev[4 * t + 2], s->stream);
+        if (r == hipSuccess)
+            r = launch_step_fused(s->p.dim, s->geom, ph, s->d.f[c], s->d.g[c], s->d.f[o], s->d.g[o], s->d.c1,
+                                  s->d.mask, s->pull, s->d.flag, s->tile_variant, s->tile_planes, s->stream);
+        if (r == hipSuccess) r = hipEventRecord(ev[4 * t + 3], s->stream);
+        if (r != hipSuccess) {
+            rc = fail(DSM_EDEVICE, std::string("dsm_step_timed: ") + hipGetErrorString(r));
+            break;
+        }
+        s->cur = o;
+        s->pull = 1;
+        ++s->steps;
+    }
+    double sum_step = 0.0, sum_links = 0.0;
+    if (!rc) {
+        hipError_t r = hipStreamSynchronize(s->stream);
+        for (int t = 0; t < n && r == hipSuccess; ++t) {
+            float a = 0.f, b = 0.f;
+            r = hipEventElapsedTime(&a, ev[4 * t], ev[4 * t + 1]);
+            if (r == hipSuccess) r = hipEventElapsedTime(&b, ev[4 * t + 2], ev[4 * t + 3]);
+            sum_links += a;
+            sum_step += b;
+        }
+        if (r != hipSuccess) rc = fail(DSM_EDEVICE, std::string("dsm_step_timed: ") + hipGetErrorString(r));
+    }
+    destroy();
+    if (rc) return rc;
+    if (step_ms) *step_ms = sum_step / n;
+    if (links_ms) *links_ms = sum_links / n;
+    return check_flag(s);
 }
 
 int dsm_free_energy(dsm_sim* s, double* F, double* E_kin) {
