@@ -48,11 +48,13 @@ def kernel_source_hash() -> str:
 
 
 def bytes_per_node(Q: int, pop_bytes: int, solid: bool) -> int:
-    """Algorithmic HBM bytes the fused kernel moves for one node: a fluid node
-    reads and writes every f and g population once and reads the frozen C1;
-    a solid node has no f (none read, none written), only g and C1."""
-    npop = Q if solid else 2 * Q
-    return 2 * npop * pop_bytes + 4
+    """Algorithmic HBM bytes the fused kernel moves for one node: every g
+    population read once and written once (the Q - 1 moving ones at pop_bytes,
+    the rest population in FP64), the same for f at fluid nodes (a solid node
+    has no f), and one read of the frozen C1."""
+    g = 2 * ((Q - 1) * pop_bytes + 8)
+    f = 0 if solid else 2 * Q * pop_bytes
+    return g + f + 4
 
 
 def bytes_per_launch(Q: int, pop_bytes: int, fluid_nodes: int, solid_nodes: int) -> int:

@@ -80,9 +80,10 @@ Layout make_layout(const dsm_params* p) {
         return at;
     };
     L.off_f[0] = take(Q * N * sizeof(float));
-    L.off_g[0] = take(Q * N * sizeof(float));
+    const size_t gbytes = (size_t)g_float_bytes((int)Q, (long long)N) + N * sizeof(double);
+    L.off_g[0] = take(gbytes);
     L.off_f[1] = take(Q * N * sizeof(float));
-    L.off_g[1] = take(Q * N * sizeof(float));
+    L.off_g[1] = take(gbytes);
     L.off_c1 = take(N * sizeof(float));
     L.off_mask = take(N);
     L.off_phi = take(N * sizeof(float));
@@ -173,7 +174,8 @@ int download_field(dsm_sim* s, const float* dev, double* host, size_t count) {
 
 // Populations: host arrays are [Q][N] (direction-major planes of nodes); the
 // device stores them row-interleaved, (row*Q + i)*X + x with n = x + X*row.
-int download_pops(dsm_sim* s, const float* dev, double* host) {
+// For g the rest population (direction 0) lives in the FP64 rest plane.
+int download_pops(dsm_sim* s, const float* dev, double* host, bool is_g) {
     const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
     s->stage_buf.resize(Q * N);
     HIP_TRY(hipMemcpyAsync(s->stage_buf.data(), dev, Q * N * sizeof(float), hipMemcpyDeviceToHost, s->stream));
@@ -181,19 +183,31 @@ int download_pops(dsm_sim* s, const float* dev, double* host) {
     for (size_t r = 0; r < rows; ++r)
         for (size_t i = 0; i < Q; ++i)
             for (size_t x = 0; x < X; ++x) host[i * N + r * X + x] = (double)s->stage_buf[(r * Q + i) * X + x];
+    if (is_g) {
+        HIP_TRY(hipMemcpyAsync(host, rest_plane(dev, (int)Q, (long long)N), N * sizeof(double),
+                               hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
     return DSM_OK;
 }
 
-int upload_pops_one(dsm_sim* s, const double* host, float* dev) {
+int upload_pops_one(dsm_sim* s, const double* host, float* dev, bool is_g) {
     const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
     s->stage_buf.resize(Q * N);
     for (size_t r = 0; r < rows; ++r)
         for (size_t i = 0; i < Q; ++i)
-            for (size_t x = 0; x < X; ++x) s->stage_buf[(r * Q + i) * X + x] = (float)host[i * N + r * X + x];
+            for (size_t x = 0; x < X; ++x)
+                s->stage_buf[(r * Q + i) * X + x] = (is_g && i == 0) ? 0.f : (float)host[i * N + r * X + x];
     HIP_TRY(hipMemcpyAsync(dev, s->stage_buf.data(), Q * N * sizeof(float), hipMemcpyHostToDevice, s->stream));
+    if (is_g)
+        HIP_TRY(hipMemcpyAsync(rest_plane(dev, (int)Q, (long long)N), host, N * sizeof(double),
+                               hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return DSM_OK;
 }
+
+// bytes of one g buffer (FP32 slots and the FP64 rest plane)
+size_t g_bytes(const dsm_sim* s) { return (size_t)g_float_bytes(s->Q, s->N) + (size_t)s->N * sizeof(double); }
 
 // The fused step leaves f of solid nodes untouched (it is never read), so the
 // spare buffer pair is cleared whenever a new state is installed: every byte of
@@ -218,8 +232,8 @@ int reduce(dsm_sim* s, double out[RED_SLOTS]) {
     int rc = observe(s);
     if (rc) return rc;
     const Phys ph = make_phys(s, s->stage);
-    HIP_TRY(launch_reduce(s->p.dim, s->geom, ph, s->d.c1, s->d.phi, s->d.mask, s->d.aux, s->d.partials,
-                          s->d.red, s->stream));
+    HIP_TRY(launch_reduce(s->p.dim, s->geom, ph, s->d.c1, s->d.phi, s->d.mask, s->d.aux, s->d.g[s->cur], s->pull,
+                          s->d.partials, s->d.red, s->stream));
     HIP_TRY(hipMemcpyAsync(out, s->d.red, RED_SLOTS * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return DSM_OK;
@@ -345,7 +359,10 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     std::vector<uint8_t> m(N, 0);
     if (mask)
         for (size_t n = 0; n < N; ++n) m[n] = mask[n] ? 1 : 0;
-    hipError_t e = hipMemcpyAsync(s->d.mask, m.data(), N, hipMemcpyHostToDevice, s->stream);
+    // every byte of the buffer starts at zero (padding and unused slots are
+    // never written later, so state images depend only on the inputs)
+    hipError_t e = hipMemsetAsync(dev_buf, 0, L.total, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d.mask, m.data(), N, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = launch_c1_from_mask(s->d.mask, s->d.c1, s->N, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -562,14 +579,14 @@ int dsm_get_populations(dsm_sim* s, double* f, double* g) {
         gs = s->d.g[o];
     }
     int rc = DSM_OK;
-    if (f) rc = download_pops(s, fs, f);
-    if (!rc && g) rc = download_pops(s, gs, g);
+    if (f) rc = download_pops(s, fs, f, false);
+    if (!rc && g) rc = download_pops(s, gs, g, true);
     return rc;
 }
 
 static int upload_pops(dsm_sim* s, const double* f, const double* g, int pair) {
-    int rc = upload_pops_one(s, f, s->d.f[pair]);
-    if (!rc) rc = upload_pops_one(s, g, s->d.g[pair]);
+    int rc = upload_pops_one(s, f, s->d.f[pair], false);
+    if (!rc) rc = upload_pops_one(s, g, s->d.g[pair], true);
     if (!rc) rc = clear_spare_f(s, 1 - pair);
     return rc;
 }
@@ -597,7 +614,7 @@ int dsm_set_postcollision(dsm_sim* s, const double* fs, const double* gs) {
 size_t dsm_state_bytes(const dsm_sim* s) {
     if (!s) return 0;
     const size_t N = (size_t)s->N, Q = (size_t)s->Q;
-    return sizeof(StateHeader) + 2 * Q * N * sizeof(float) + N * sizeof(float) + N;
+    return sizeof(StateHeader) + Q * N * sizeof(float) + g_bytes(s) + N * sizeof(float) + N;
 }
 
 int dsm_get_state(dsm_sim* s, void* host, size_t bytes) {
@@ -607,7 +624,7 @@ int dsm_get_state(dsm_sim* s, void* host, size_t bytes) {
     StateHeader h;
     memset(&h, 0, sizeof(h));
     h.magic = kStateMagic;
-    h.version = 1;
+    h.version = 2;
     h.dim = s->p.dim;
     h.nx = s->p.nx;
     h.ny = s->p.ny;
@@ -626,8 +643,8 @@ int dsm_get_state(dsm_sim* s, void* host, size_t bytes) {
     const size_t N = (size_t)s->N, QN = (size_t)s->Q * N;
     HIP_TRY(hipMemcpyAsync(o, s->d.f[s->cur], QN * sizeof(float), hipMemcpyDeviceToHost, s->stream));
     o += QN * sizeof(float);
-    HIP_TRY(hipMemcpyAsync(o, s->d.g[s->cur], QN * sizeof(float), hipMemcpyDeviceToHost, s->stream));
-    o += QN * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(o, s->d.g[s->cur], g_bytes(s), hipMemcpyDeviceToHost, s->stream));
+    o += g_bytes(s);
     HIP_TRY(hipMemcpyAsync(o, s->d.c1, N * sizeof(float), hipMemcpyDeviceToHost, s->stream));
     o += N * sizeof(float);
     HIP_TRY(hipMemcpyAsync(o, s->d.mask, N, hipMemcpyDeviceToHost, s->stream));
@@ -640,7 +657,7 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
     if (bytes != dsm_state_bytes(s)) return fail(DSM_EINVAL, "state size mismatch");
     StateHeader h;
     memcpy(&h, host, sizeof(h));
-    if (h.magic != kStateMagic || h.version != 1) return fail(DSM_EINVAL, "not a dsm state image");
+    if (h.magic != kStateMagic || h.version != 2) return fail(DSM_EINVAL, "not a dsm state image (or an older format)");
     if (h.dim != s->p.dim || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz)
         return fail(DSM_EINVAL, "state image is for another lattice");
     if (h.stage != 1 && h.stage != 2) return fail(DSM_EINVAL, "state image has no live stage");
@@ -648,8 +665,8 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
     const size_t N = (size_t)s->N, QN = (size_t)s->Q * N;
     HIP_TRY(hipMemcpyAsync(s->d.f[0], o, QN * sizeof(float), hipMemcpyHostToDevice, s->stream));
     o += QN * sizeof(float);
-    HIP_TRY(hipMemcpyAsync(s->d.g[0], o, QN * sizeof(float), hipMemcpyHostToDevice, s->stream));
-    o += QN * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(s->d.g[0], o, g_bytes(s), hipMemcpyHostToDevice, s->stream));
+    o += g_bytes(s);
     HIP_TRY(hipMemcpyAsync(s->d.c1, o, N * sizeof(float), hipMemcpyHostToDevice, s->stream));
     o += N * sizeof(float);
     HIP_TRY(hipMemcpyAsync(s->d.mask, o, N, hipMemcpyHostToDevice, s->stream));

@@ -30,6 +30,16 @@
 // row is uniform, so the 9 source rows of a pull are scalar base addresses
 // and the lanes only add their (wrapped) x - 1, x, x + 1.
 //
+// Mass.  BGK conserves sum_i g_i at each node and streaming only moves
+// values, so the liquid mass is exact up to rounding.  The rest population
+// g_0, which carries nearly all of C, is stored in FP64 (dsm_lattice.h); C is
+// summed in FP64 and the post-collision rest population is written as
+// C - sum_{i>0} g*_i, equal to g_0 - (g_0 - g_eq,0)/tau_g in real arithmetic.
+// The stored populations of a node then keep its C to FP64 rounding: with
+// g_0 in FP32, rounding at the scale of C (~1e-7 relative per node and step)
+// is systematic wherever the moving populations are below half an ulp of C,
+// and the liquid mass drifts by ~1e-3 over 10^5 steps.
+//
 // Interpolated bounce-back.  A fluid node x pulls f_i from x - c_i; when that
 // node is solid, the slot holds no population of its own, and the link kernel
 // (dsm_links.hip) has already written the bounce-back value for x into it
@@ -168,9 +178,11 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 
     const float fpref3 = 3.f * ph.fpref;
     const float k13 = ph.k1 + ph.k3;
+    const double* __restrict__ g0src = rest_plane(gsrc, Q, g.N);
+    double* __restrict__ g0dst = rest_plane(gdst, Q, g.N);
     float gA[Q], gB[Q];
 
-    auto iteration = [&](int j, float (&gload)[Q], float (&gcoll)[Q]) {
+    auto iteration = [&](int j, float (&gload)[Q], float (&gcoll)[Q], double& cload, double& ccoll) {
         const int l = z0 - 1 + j;  // lead plane
         const int c = l - 1;       // collision plane (valid when j >= 2)
         const int lz = pmod(l, Z);
@@ -183,42 +195,52 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
         // ---- phase 1 --------------------------------------------------------
         const __amdgpu_buffer_rsrc_t gl[3] = {plane_rsrc(gsrc, PL, zl[0]), plane_rsrc(gsrc, PL, zl[1]),
                                               plane_rsrc(gsrc, PL, zl[2])};
-        // lead plane, own column: pulled g and their sum
+        // lead plane, own column: pulled moving g, the (FP64) rest population
+        // of the node, and C = g_0 + sum_{i>0} g_i in FP64
         {
-            float acc = 0.f;
+            const long long node = xv[1] + X * ((long long)yv[1] + (long long)Y * lz);
+            const double r0 = g0src[node];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
+            for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
                 gload[i] = bload(gl[sz], xb[sx], 4u * (unsigned)(yv[sy] * QX + i * X));
             }
+            double acc = 0.0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) acc += gload[i];
-            s_c[sl][rint] = acc;
-            if (STAGE == 2) s_c1[sl][rint] = c1g[xv[1] + X * ((long long)yv[1] + (long long)Y * lz)];
+            for (int i = 1; i < Q; ++i) acc += (double)gload[i];
+            cload = r0 + acc;
+            s_c[sl][rint] = (float)cload;
+            if (STAGE == 2) s_c1[sl][rint] = c1g[node];
         }
         // lead plane, halo columns (same summation order as the own column)
         if (row_halo) {
-            float h[Q], acc = 0.f;
+            const long long node = xv[1] + X * ((long long)hyw + (long long)Y * lz);
+            const double r0 = g0src[node];
+            float h[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
+            for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
                 h[i] = bload(gl[sz], xb[sx], 4u * (unsigned)(hyv[sy] * QX + i * X));
             }
+            double acc = 0.0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) acc += h[i];
-            s_c[sl][hreg] = acc;
-            if (STAGE == 2) s_c1[sl][hreg] = c1g[xv[1] + X * ((long long)hyw + (long long)Y * lz)];
+            for (int i = 1; i < Q; ++i) acc += (double)h[i];
+            s_c[sl][hreg] = (float)(r0 + acc);
+            if (STAGE == 2) s_c1[sl][hreg] = c1g[node];
         } else if (side) {
-            float h[Q], acc = 0.f;
+            const long long node = sxw + X * ((long long)syw + (long long)Y * lz);
+            const double r0 = g0src[node];
+            float h[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
+            for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
                 h[i] = bload(gl[sz], 4u * (unsigned)(syv[sy] * QX + i * X + sxv[sx]), 0u);
             }
+            double acc = 0.0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) acc += h[i];
-            s_c[sl][sreg] = acc;
-            if (STAGE == 2) s_c1[sl][sreg] = c1g[sxw + X * ((long long)syw + (long long)Y * lz)];
+            for (int i = 1; i < Q; ++i) acc += (double)h[i];
+            s_c[sl][sreg] = (float)(r0 + acc);
+            if (STAGE == 2) s_c1[sl][sreg] = c1g[node];
         }
         // collision plane: f (in flight across the barrier)
         bool solid = false;
@@ -313,22 +335,26 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
             }
         }
         const __amdgpu_buffer_rsrc_t go = plane_rsrc(gdst, PL, c);
-        float restg = C;
+        // moving populations first; the rest population takes what is left of
+        // C (FP64), so the stored populations of the node keep its C
+        double moved = 0.0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
             const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
-            restg -= geq;
-            bstore_nt(go, xb[1], own_off + 4u * (unsigned)(i * X), gcoll[i] - (gcoll[i] - geq) * ph.inv_taug);
+            const float gs = gcoll[i] - (gcoll[i] - geq) * ph.inv_taug;
+            moved += (double)gs;
+            bstore_nt(go, xb[1], own_off + 4u * (unsigned)(i * X), gs);
         }
-        bstore_nt(go, xb[1], own_off, gcoll[0] - (gcoll[0] - restg) * ph.inv_taug);
+        __builtin_nontemporal_store(ccoll - moved, g0dst + (xv[1] + X * ((long long)yv[1] + (long long)Y * c)));
         if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
     };
 
+    double cA = 0.0, cB = 0.0;  // FP64 C of the own column, lead and collision plane
     const int J = zlen + 2;
     for (int j = 0; j < J; j += 2) {
-        iteration(j, gA, gB);
-        if (j + 1 < J) iteration(j + 1, gB, gA);
+        iteration(j, gA, gB, cA, cB);
+        if (j + 1 < J) iteration(j + 1, gB, gA, cB, cA);
     }
 }
 

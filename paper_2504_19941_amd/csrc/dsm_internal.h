@@ -69,8 +69,8 @@ hipError_t launch_pull_state(int dim, const Geom& g, const Phys& ph, const float
                              const float* gsrc, const float* c1, float* fdst, float* gdst,
                              hipStream_t st);
 hipError_t launch_reduce(int dim, const Geom& g, const Phys& ph, const float* c1, const float* phi,
-                         const uint8_t* mask, const float* aux, double* partials, double* red,
-                         hipStream_t st);
+                         const uint8_t* mask, const float* aux, const float* gsrc, int pull, double* partials,
+                         double* red, hipStream_t st);
 
 // --- interpolated bounce-back (dsm_links.hip) ------------------------------
 // find: lists the fluid nodes with cut links (C1 fixed), count[0] entries;

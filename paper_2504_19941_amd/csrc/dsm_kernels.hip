@@ -162,13 +162,13 @@ __global__ void k_moment(Geom g, const float* __restrict__ gsrc, float* __restri
     if (n >= g.N) return;
     int x, y, z;
     decode(g, n, x, y, z);
-    float acc = 0.f;
+    double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
+    for (int i = 1; i < L::Q; ++i) {
         long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
-        acc += gsrc[pop_index(g, L::Q, i, src)];
+        acc += (double)gsrc[pop_index(g, L::Q, i, src)];
     }
-    phi[n] = acc;
+    phi[n] = (float)(rest_plane(gsrc, L::Q, g.N)[n] + acc);
 }
 
 // chemical potential of the fluid stage (mu = dPsi/dC2) or of the solid stage
@@ -284,21 +284,26 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
         }
     }
     const float m = mu[n];
-    float rest = C;
     float gi[Q];
+    double C64 = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
         long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
         gi[i] = gsrc[pop_index(g, L::Q, i, src)];
+        C64 += (double)gi[i];
     }
+    C64 += rest_plane(gsrc, Q, N)[n];
+    // rest population (FP64) = C - sum of the moving post-collision populations
+    double moved = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
         float geq = L::w[i] * m + L::w[i] * C * s_i(cu, uu);
-        rest -= geq;
-        gdst[pop_index(g, L::Q, i, n)] = gi[i] - (gi[i] - geq) * ph.inv_taug;
+        float gs = gi[i] - (gi[i] - geq) * ph.inv_taug;
+        moved += (double)gs;
+        gdst[pop_index(g, L::Q, i, n)] = gs;
     }
-    gdst[pop_index(g, L::Q, 0, n)] = gi[0] - (gi[0] - rest) * ph.inv_taug;
+    rest_plane(gdst, Q, N)[n] = C64 - moved;
     if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
 }
 
@@ -309,15 +314,17 @@ __global__ void k_init_populations(Geom g, const float* __restrict__ phi, const 
     using L = Lattice<D>;
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
-    float C = phi[n], m = mu[n], rest = C;
+    const float C = phi[n], m = mu[n];
+    double moved = 0.0;
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
-        float geq = L::w[i] * m;
-        rest -= geq;
+        const float geq = L::w[i] * m;
+        moved += (double)geq;
         gdst[pop_index(g, L::Q, i, n)] = geq;
         fdst[pop_index(g, L::Q, i, n)] = 0.f;
     }
-    gdst[pop_index(g, L::Q, 0, n)] = rest;
+    gdst[pop_index(g, L::Q, 0, n)] = 0.f;  // unused slot: the rest population is FP64
+    rest_plane(gdst, L::Q, g.N)[n] = (double)C - moved;
     fdst[pop_index(g, L::Q, 0, n)] = 0.f;
 }
 
@@ -332,7 +339,9 @@ __global__ void k_pull_state(Geom g, Phys ph, const float* __restrict__ fsrc, co
     int x, y, z;
     decode(g, n, x, y, z);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gdst[pop_index(g, L::Q, i, n)] = gsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
+    for (int i = 1; i < Q; ++i) gdst[pop_index(g, L::Q, i, n)] = gsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
+    gdst[pop_index(g, L::Q, 0, n)] = 0.f;
+    rest_plane(gdst, Q, g.N)[n] = rest_plane(gsrc, Q, g.N)[n];
     const bool solid = ph.stage == 2 && c1[n] > 0.5f;
     float f[Q];
     if (solid) {
@@ -368,6 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(Geom g, Phys ph, const float*
                                                    const float* __restrict__ phi,
                                                    const uint8_t* __restrict__ mask,
                                                    const float* __restrict__ aux,
+                                                   const float* __restrict__ gsrc, int pull,
                                                    double* __restrict__ partials) {
     using L = Lattice<D>;
     const long long N = g.N;
@@ -386,9 +396,17 @@ __global__ void __launch_bounds__(kBlock) k_reduce(Geom g, Phys ph, const float*
             C2 = 0.0;
         }
         double C3 = 1.0 - C1 - C2;
-        acc[RED_C1] += C1;
-        acc[RED_C2] += C2;
-        acc[RED_C3] += C3;
+        // masses: the evolving component summed in FP64 from the stored
+        // populations themselves, so that drift measures the stored state
+        double cm = rest_plane(gsrc, L::Q, N)[n];
+        for (int i = 1; i < L::Q; ++i) {
+            const long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
+            cm += (double)gsrc[pop_index(g, L::Q, i, src)];
+        }
+        const double m1 = ph.stage == 2 ? C1 : cm, m2 = ph.stage == 2 ? cm : 0.0;
+        acc[RED_C1] += m1;
+        acc[RED_C2] += m2;
+        acc[RED_C3] += 1.0 - m1 - m2;
         double e;
         if (ph.stage == 2) {
             e = 0.5 * ph.k2 * C2 * C2 * (1.0 - C2) * (1.0 - C2) + 0.5 * ph.k3 * C3 * C3 * (1.0 - C3) * (1.0 - C3);
@@ -538,10 +556,12 @@ hipError_t launch_pull_state(int dim, const Geom& g, const Phys& ph, const float
 }
 
 hipError_t launch_reduce(int dim, const Geom& g, const Phys& ph, const float* c1, const float* phi,
-                         const uint8_t* mask, const float* aux, double* partials, double* red, hipStream_t st) {
+                         const uint8_t* mask, const float* aux, const float* gsrc, int pull, double* partials,
+                         double* red, hipStream_t st) {
     long long want = (g.N + kBlock - 1) / kBlock;
     int blocks = (int)(want < kReduceBlocks ? (want < 1 ? 1 : want) : kReduceBlocks);
-    DSM_DISPATCH(dim, k_reduce, dim3(blocks), dim3(kBlock), 0, st, g, ph, c1, phi, mask, aux, partials);
+    DSM_DISPATCH(dim, k_reduce, dim3(blocks), dim3(kBlock), 0, st, g, ph, c1, phi, mask, aux, gsrc, pull,
+                 partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, blocks, red);
     return hipGetLastError();
 }

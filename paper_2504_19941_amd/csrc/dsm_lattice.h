@@ -74,6 +74,22 @@ __device__ __forceinline__ long long node_index(const Geom& g, int x, int y, int
 // direction-major, so population i of node n = x + X*row lives at
 // (row*Q + i)*X + x.  A wave reading one direction of one row segment then
 // touches one contiguous run, and a node's Q values sit within Q*X floats.
+// The g populations of one buffer: the Q*N FP32 slots above, of which the
+// moving directions i > 0 are used, followed (256-byte aligned) by the rest
+// population g_0 of every node in FP64, node order.  The rest population
+// carries nearly all of C, so storing it in FP64 keeps the liquid mass from
+// drifting by FP32 rounding at the scale of C (the moving populations are
+// small and their rounding is negligible).
+__host__ __device__ __forceinline__ long long g_float_bytes(int Q, long long N) {
+    return ((long long)Q * N * 4 + 255) / 256 * 256;
+}
+__host__ __device__ __forceinline__ double* rest_plane(float* g, int Q, long long N) {
+    return reinterpret_cast<double*>(reinterpret_cast<char*>(g) + g_float_bytes(Q, N));
+}
+__host__ __device__ __forceinline__ const double* rest_plane(const float* g, int Q, long long N) {
+    return reinterpret_cast<const double*>(reinterpret_cast<const char*>(g) + g_float_bytes(Q, N));
+}
+
 __host__ __device__ __forceinline__ long long pop_index(const Geom& g, int Q, int i, long long n) {
     const long long row = n / g.X;
     return (row * Q + i) * g.X + (n - row * g.X);

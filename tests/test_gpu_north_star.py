@@ -57,7 +57,7 @@ def test_1000_steps_match_oracle(gpu, dim, shape):
     m1 = sim.mass()
     drift = abs(m1[1] - m0[1]) / m0[1]
     print(f"  liquid mass drift {drift:.2e}", flush=True)
-    assert drift < 1e-6
+    assert drift < 1e-9
     mo = orc.mass()
     assert abs(m1[1] - mo[1]) / mo[1] < 1e-6
 
@@ -198,4 +198,4 @@ def test_contact_angle_matches_oracle_and_young(gpu, theta):
     assert abs(th - theta) < 2.0
     drift = abs(sim.mass()[1] - m0[1]) / m0[1]
     print(f"  liquid mass drift after {done} steps: {drift:.2e}", flush=True)
-    assert drift < 1e-5
+    assert drift < 1e-9
