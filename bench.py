@@ -82,16 +82,17 @@ def measured_traffic(workload: str, nodes: int):
 
 
 def cpu_baseline(w, seconds: float):
-    """The FP64 oracle on this host's cores, on the same lattice, for about
-    ``seconds`` of CPU work."""
+    """The FP64 oracle on this host's cores, on the same lattice from the same
+    initial state, for about ``seconds`` of CPU work.  Returns the report and
+    (total steps, oracle C2 after them) for the accuracy check."""
     from oracle.oracle import Oracle
     from paper_2504_19941_amd import workloads as W
 
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     threads = max(1, min(threads, 16))
     o = Oracle(w.dim, w.shape, w.kappa, tau=w.tau, mobility=w.mobility, threads=threads)
-    o.set_solid_field(W.flat(w.C1))
-    o.set_liquid(W.flat(w.C2))
+    o.set_solid_field(f32(W.flat(w.C1)))
+    o.set_liquid(f32(W.flat(w.C2)))
     t0 = time.perf_counter()
     o.step(1)
     dt = time.perf_counter() - t0
@@ -101,8 +102,9 @@ def cpu_baseline(w, seconds: float):
         o.step(more)
     dt_more = time.perf_counter() - t0
     steps, total = (more, dt_more) if more else (1, dt)
+    C2 = o.fields()["C2"]
     o.close()
-    return {
+    report = {
         "value": round(w.nodes * steps / total / 1e6, 4),
         "unit": "MLUPS",
         "cores": threads,
@@ -110,6 +112,69 @@ def cpu_baseline(w, seconds: float):
         "sample": f"{w.name}: {steps} FP64 oracle steps after 1 untimed, {threads} OpenMP threads, "
                   f"{total:.1f} s",
     }
+    return report, 1 + more, C2
+
+
+def f32(a):
+    import numpy as np
+
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def run_storage(dsm, W, w, dev, storage, args, fluid_nodes, solid_nodes):
+    """Times the step for one population storage mode: timed region 1 is K
+    whole steps bracketed by events (throughput), timed region 2 the same with
+    HIP events around every launch (per-launch kernel duration)."""
+    import torch
+
+    sim = dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
+                         reduce_every=0, device=dev, storage=storage)
+    if args.tile is not None or args.planes is not None:
+        sim.set_tiling(args.tile or 0, args.planes or 16)
+    sim.set_solid_field(f32(W.flat(w.C1)))
+    sim.set_liquid(f32(W.flat(w.C2)))
+    m0 = sim.mass()
+    stream = sim.stream
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1) / max(args.steps, 1)
+    fused_ms, links_ms = sim.step_timed(args.steps)
+    m1 = sim.mass()
+    sim.close()
+    pop_bytes = 2 if storage == dsm.DSM_STORAGE_FP16 else 4
+    alg = bytes_per_launch(19 if w.dim == 3 else 9, pop_bytes, fluid_nodes, solid_nodes)
+    return {
+        "mlups": w.nodes / (ms * 1e-3) / 1e6,
+        "ms": ms,
+        "wall": wall,
+        "fused_ms": fused_ms,
+        "links_ms": links_ms,
+        "alg_bytes": alg,
+        "achieved": alg / (fused_ms * 1e-3) / 1e9,
+        "drift": abs(m1[1] - m0[1]) / abs(m0[1]),
+    }
+
+
+def error_vs_oracle(dsm, W, w, dev, storage, steps, C2_oracle):
+    import numpy as np
+
+    sim = dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
+                         reduce_every=0, device=dev, storage=storage)
+    sim.set_solid_field(f32(W.flat(w.C1)))
+    sim.set_liquid(f32(W.flat(w.C2)))
+    sim.step(steps)
+    err = float(np.abs(sim.fields()["C2"] - C2_oracle).max())
+    sim.close()
+    return err
 
 
 def main():
@@ -146,36 +211,10 @@ def main():
 
     w = W.config_3d_sessile(args.theta, n=128)
     Q = 19
-    sim = dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
-                         reduce_every=0, device=dev)
-    if args.tile is not None or args.planes is not None:
-        sim.set_tiling(args.tile or 0, args.planes or 16)
-    sim.set_solid_field(W.flat(w.C1))
-    sim.set_liquid(W.flat(w.C2))
     solid_nodes = int((np.asarray(w.C1, dtype=np.float32) > 0.5).sum())
     fluid_nodes = w.nodes - solid_nodes
-    m0 = sim.mass()
-    stream = sim.stream
-
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    # timed region 1: whole steps (link kernel + fused kernel), no extra events
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = e0.elapsed_time(e1)
-    ms = ms_total / max(args.steps, 1)
-    # timed region 2: the same steps with HIP events around every launch on
-    # the library's stream, for the per-launch duration of the fused kernel
-    fused_ms, links_ms = sim.step_timed(args.steps)
-    m1 = sim.mass()
-    drift = abs(m1[1] - m0[1]) / abs(m0[1])
+    r32 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP32, args, fluid_nodes, solid_nodes)
+    r16 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP16, args, fluid_nodes, solid_nodes)
 
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -187,9 +226,11 @@ def main():
         del a, b
 
     N = w.nodes
-    mlups = N / (ms * 1e-3) / 1e6
-    alg_bytes = bytes_per_launch(Q, 4, fluid_nodes, solid_nodes)
-    achieved = alg_bytes / (fused_ms * 1e-3) / 1e9
+    ms = r32["ms"]
+    mlups = r32["mlups"]
+    alg_bytes = r32["alg_bytes"]
+    achieved = r32["achieved"]
+    fused_ms, links_ms, drift, wall = r32["fused_ms"], r32["links_ms"], r32["drift"], r32["wall"]
     traffic = measured_traffic(w.name, N)
     out = {
         "metric": METRIC,
@@ -208,7 +249,7 @@ def main():
             "workload": w.name,
             "lattice": "D3Q19",
             "shape": list(w.shape),
-            "storage": "fp32",
+            "storage": "fp32 (fp16 in fp16_store)",
             "fluid_node_fraction": round(fluid_nodes / N, 4),
             "tau": w.tau,
             "mobility": w.mobility,
@@ -231,8 +272,26 @@ def main():
             "kernel": "k_step_fused<3,...> (one launch per step)",
         },
     }
+    out["fp16_store"] = {
+        "value": round(r16["mlups"], 2),
+        "unit": "MLUPS",
+        "ms_per_step": round(r16["ms"], 5),
+        "fused_kernel_us": round(r16["fused_ms"] * 1e3, 2),
+        "link_kernel_us": round(r16["links_ms"] * 1e3, 2),
+        "hbm_GBps": round(r16["achieved"], 1),
+        "hbm_frac": round(r16["achieved"] / HBM_PEAK_GBPS, 4),
+        "algorithmic_bytes": r16["alg_bytes"],
+        "speedup_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
+        "liquid_mass_drift_rel": r16["drift"],
+    }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        report, steps, C2o = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = report
+        out["error_vs_oracle"] = {
+            "steps": steps,
+            "fp32_max_abs_dC2": error_vs_oracle(dsm, W, w, dev, dsm.DSM_STORAGE_FP32, steps, C2o),
+            "fp16_max_abs_dC2": error_vs_oracle(dsm, W, w, dev, dsm.DSM_STORAGE_FP16, steps, C2o),
+        }
     print(json.dumps(out), flush=True)
 
 

@@ -65,6 +65,16 @@ enum { DSM_SOLID_RESET = 1, DSM_SOLID_REMASK = 2 };
  * (moment, chemical potential, collide-stream) kept as a cross-check */
 enum { DSM_KERNEL_FUSED = 0, DSM_KERNEL_SPLIT = 1 };
 
+/* population storage in device memory.  Arithmetic is FP32 either way.
+ * FP16 stores every f and every moving g (i > 0) as an FP16 number holding
+ * 4096 times the value (the populations of this scheme are deviations from
+ * the rest state: f vanishes at rest and the moving g are small), which
+ * halves the population traffic.  The rest population g_0, which carries
+ * nearly all of the concentration C, is kept in FP64 in both modes and is
+ * written as C minus the stored moving populations, so the component masses
+ * are conserved to FP64 rounding in both modes. */
+enum { DSM_STORAGE_FP32 = 0, DSM_STORAGE_FP16 = 1 };
+
 typedef struct {
     int dim;             /* 2 (D2Q9, nz must be 1) or 3 (D3Q19)                  */
     int nx, ny, nz;      /* lattice size, each >= 4 (nz = 1 in 2D)               */
@@ -79,6 +89,7 @@ typedef struct {
     int reduce_every;    /* K > 0: dsm_step checks for non-finite values every
                             K steps (synchronising); 0 disables the check        */
     int kernel;          /* DSM_KERNEL_FUSED (default) or DSM_KERNEL_SPLIT        */
+    int storage;         /* DSM_STORAGE_FP32 (default) or DSM_STORAGE_FP16        */
 } dsm_params;
 
 typedef struct dsm_sim dsm_sim;

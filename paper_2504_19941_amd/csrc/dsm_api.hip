@@ -60,6 +60,7 @@ const char* validate(const dsm_params* p) {
     if (p->dim == 2 && p->gravity[2] != 0.0) return "gravity[2] must be 0 when dim == 2";
     if (p->reduce_every < 0) return "reduce_every must be >= 0";
     if (p->kernel != DSM_KERNEL_FUSED && p->kernel != DSM_KERNEL_SPLIT) return "unknown kernel";
+    if (p->storage != DSM_STORAGE_FP32 && p->storage != DSM_STORAGE_FP16) return "unknown storage";
     return nullptr;
 }
 
@@ -79,10 +80,12 @@ Layout make_layout(const dsm_params* p) {
         o = align_up(o + bytes);
         return at;
     };
-    L.off_f[0] = take(Q * N * sizeof(float));
-    const size_t gbytes = (size_t)g_float_bytes((int)Q, (long long)N) + N * sizeof(double);
+    const int es = p->storage == DSM_STORAGE_FP16 ? 2 : 4;
+    const size_t fbytes = (size_t)pop_bytes((int)Q, (long long)N, es);
+    L.off_f[0] = take(fbytes);
+    const size_t gbytes = fbytes + N * sizeof(double);
     L.off_g[0] = take(gbytes);
-    L.off_f[1] = take(Q * N * sizeof(float));
+    L.off_f[1] = take(fbytes);
     L.off_g[1] = take(gbytes);
     L.off_c1 = take(N * sizeof(float));
     L.off_mask = take(N);
@@ -124,7 +127,10 @@ struct dsm_sim {
     int nlinks;        // boundary nodes with cut links (fluid stage)
     int tile_variant;  // workgroup tile of the fused step
     int tile_planes;   // planes marched per workgroup
+    int half;      // populations stored in FP16 (value * kHalfScale)
+    int es;        // bytes per population element
     std::vector<float> stage_buf;  // host staging for conversions
+    std::vector<uint16_t> stage16;
 };
 
 namespace {
@@ -174,46 +180,82 @@ int download_field(dsm_sim* s, const float* dev, double* host, size_t count) {
 
 // Populations: host arrays are [Q][N] (direction-major planes of nodes); the
 // device stores them row-interleaved, (row*Q + i)*X + x with n = x + X*row.
-// For g the rest population (direction 0) lives in the FP64 rest plane.
-int download_pops(dsm_sim* s, const float* dev, double* host, bool is_g) {
-    const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
-    s->stage_buf.resize(Q * N);
-    HIP_TRY(hipMemcpyAsync(s->stage_buf.data(), dev, Q * N * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+// Population buffers as the kernels take them.
+Pop PF(const dsm_sim* s, int k) { return Pop{s->d.f[k], s->half}; }
+Pop PG(const dsm_sim* s, int k) { return Pop{s->d.g[k], s->half}; }
+size_t f_bytes(const dsm_sim* s) { return (size_t)pop_bytes(s->Q, s->N, s->es); }
+size_t g_bytes(const dsm_sim* s) { return f_bytes(s) + (size_t)s->N * sizeof(double); }
+
+// Element copies between the device layout and FP32 host staging (FP16
+// elements hold value * kHalfScale).
+int fetch_elems(dsm_sim* s, const void* dev, size_t count) {
+    s->stage_buf.resize(count);
+    if (!s->half) {
+        HIP_TRY(hipMemcpyAsync(s->stage_buf.data(), dev, count * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        return DSM_OK;
+    }
+    s->stage16.resize(count);
+    HIP_TRY(hipMemcpyAsync(s->stage16.data(), dev, count * 2, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t k = 0; k < count; ++k)
+        s->stage_buf[k] = __half2float(__ushort_as_half(s->stage16[k])) * (1.f / kHalfScale);
+    return DSM_OK;
+}
+
+int send_elems(dsm_sim* s, void* dev, size_t count) {
+    if (!s->half) {
+        HIP_TRY(hipMemcpyAsync(dev, s->stage_buf.data(), count * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        return DSM_OK;
+    }
+    s->stage16.resize(count);
+    for (size_t k = 0; k < count; ++k) s->stage16[k] = __half_as_ushort(__float2half(s->stage_buf[k] * kHalfScale));
+    HIP_TRY(hipMemcpyAsync(dev, s->stage16.data(), count * 2, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return DSM_OK;
+}
+
+// Populations: host arrays are [Q][N] (direction-major planes of nodes); the
+// device stores them row-interleaved, (row*Q + i)*X + x with n = x + X*row.
+// For g the rest population (direction 0) lives in the FP64 rest plane.
+int download_pops(dsm_sim* s, const void* dev, double* host, bool is_g) {
+    const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
+    int rc = fetch_elems(s, dev, Q * N);
+    if (rc) return rc;
     for (size_t r = 0; r < rows; ++r)
         for (size_t i = 0; i < Q; ++i)
             for (size_t x = 0; x < X; ++x) host[i * N + r * X + x] = (double)s->stage_buf[(r * Q + i) * X + x];
     if (is_g) {
-        HIP_TRY(hipMemcpyAsync(host, rest_plane(dev, (int)Q, (long long)N), N * sizeof(double),
+        HIP_TRY(hipMemcpyAsync(host, rest_plane(dev, (int)Q, (long long)N, s->es), N * sizeof(double),
                                hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
     return DSM_OK;
 }
 
-int upload_pops_one(dsm_sim* s, const double* host, float* dev, bool is_g) {
+int upload_pops_one(dsm_sim* s, const double* host, void* dev, bool is_g) {
     const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
     s->stage_buf.resize(Q * N);
     for (size_t r = 0; r < rows; ++r)
         for (size_t i = 0; i < Q; ++i)
             for (size_t x = 0; x < X; ++x)
                 s->stage_buf[(r * Q + i) * X + x] = (is_g && i == 0) ? 0.f : (float)host[i * N + r * X + x];
-    HIP_TRY(hipMemcpyAsync(dev, s->stage_buf.data(), Q * N * sizeof(float), hipMemcpyHostToDevice, s->stream));
-    if (is_g)
-        HIP_TRY(hipMemcpyAsync(rest_plane(dev, (int)Q, (long long)N), host, N * sizeof(double),
+    int rc = send_elems(s, dev, Q * N);
+    if (rc) return rc;
+    if (is_g) {
+        HIP_TRY(hipMemcpyAsync(rest_plane(dev, (int)Q, (long long)N, s->es), host, N * sizeof(double),
                                hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
     return DSM_OK;
 }
-
-// bytes of one g buffer (FP32 slots and the FP64 rest plane)
-size_t g_bytes(const dsm_sim* s) { return (size_t)g_float_bytes(s->Q, s->N) + (size_t)s->N * sizeof(double); }
 
 // The fused step leaves f of solid nodes untouched (it is never read), so the
 // spare buffer pair is cleared whenever a new state is installed: every byte of
 // the state then depends only on the inputs.
 int clear_spare_f(dsm_sim* s, int spare) {
-    HIP_TRY(hipMemsetAsync(s->d.f[spare], 0, (size_t)s->Q * (size_t)s->N * sizeof(float), s->stream));
+    HIP_TRY(hipMemsetAsync(s->d.f[spare], 0, f_bytes(s), s->stream));
     return DSM_OK;
 }
 
@@ -221,9 +263,9 @@ int clear_spare_f(dsm_sim* s, int spare) {
 int observe(dsm_sim* s) {
     const Phys ph = make_phys(s, s->stage);
     const int c = s->cur;
-    HIP_TRY(launch_moment(s->p.dim, s->geom, s->d.g[c], s->d.phi, s->pull, s->stream));
+    HIP_TRY(launch_moment(s->p.dim, s->geom, PG(s, c), s->d.phi, s->pull, s->stream));
     HIP_TRY(launch_mu(s->p.dim, s->geom, ph, s->d.phi, s->d.c1, s->d.mask, s->d.mu, s->stream));
-    HIP_TRY(launch_observe(s->p.dim, s->geom, ph, s->d.f[c], s->d.c1, s->d.phi, s->d.mu, s->pull, s->d.aux,
+    HIP_TRY(launch_observe(s->p.dim, s->geom, ph, PF(s, c), s->d.c1, s->d.phi, s->d.mu, s->pull, s->d.aux,
                            s->stream));
     return DSM_OK;
 }
@@ -232,7 +274,7 @@ int reduce(dsm_sim* s, double out[RED_SLOTS]) {
     int rc = observe(s);
     if (rc) return rc;
     const Phys ph = make_phys(s, s->stage);
-    HIP_TRY(launch_reduce(s->p.dim, s->geom, ph, s->d.c1, s->d.phi, s->d.mask, s->d.aux, s->d.g[s->cur], s->pull,
+    HIP_TRY(launch_reduce(s->p.dim, s->geom, ph, s->d.c1, s->d.phi, s->d.mask, s->d.aux, PG(s, s->cur), s->pull,
                           s->d.partials, s->d.red, s->stream));
     HIP_TRY(hipMemcpyAsync(out, s->d.red, RED_SLOTS * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -264,13 +306,13 @@ int one_step(dsm_sim* s) {
     const int c = s->cur, n = 1 - s->cur;
     if (s->p.kernel == DSM_KERNEL_FUSED) {
         if (s->stage == 2 && s->pull)
-            HIP_TRY(launch_bounce(s->d.f[c], s->d.links, s->nlinks, s->stream));
-        HIP_TRY(launch_step_fused(s->p.dim, s->geom, ph, s->d.f[c], s->d.g[c], s->d.f[n], s->d.g[n], s->d.c1,
+            HIP_TRY(launch_bounce(PF(s, c), s->d.links, s->nlinks, s->stream));
+        HIP_TRY(launch_step_fused(s->p.dim, s->geom, ph, PF(s, c), PG(s, c), PF(s, n), PG(s, n), s->d.c1,
                                   s->d.mask, s->pull, s->d.flag, s->tile_variant, s->tile_planes, s->stream));
     } else {
-        HIP_TRY(launch_moment(s->p.dim, s->geom, s->d.g[c], s->d.phi, s->pull, s->stream));
+        HIP_TRY(launch_moment(s->p.dim, s->geom, PG(s, c), s->d.phi, s->pull, s->stream));
         HIP_TRY(launch_mu(s->p.dim, s->geom, ph, s->d.phi, s->d.c1, s->d.mask, s->d.mu, s->stream));
-        HIP_TRY(launch_collide_split(s->p.dim, s->geom, ph, s->d.f[c], s->d.g[c], s->d.f[n], s->d.g[n],
+        HIP_TRY(launch_collide_split(s->p.dim, s->geom, ph, PF(s, c), PG(s, c), PF(s, n), PG(s, n),
                                      s->d.c1, s->d.phi, s->d.mu, s->pull, s->d.flag, s->stream));
     }
     s->cur = n;
@@ -282,7 +324,7 @@ int one_step(dsm_sim* s) {
 int init_populations(dsm_sim* s, int stage) {
     const Phys ph = make_phys(s, stage);
     HIP_TRY(launch_mu(s->p.dim, s->geom, ph, s->d.phi, s->d.c1, s->d.mask, s->d.mu, s->stream));
-    HIP_TRY(launch_init_populations(s->p.dim, s->geom, s->d.phi, s->d.mu, s->d.f[0], s->d.g[0], s->stream));
+    HIP_TRY(launch_init_populations(s->p.dim, s->geom, s->d.phi, s->d.mu, PF(s, 0), PG(s, 0), s->stream));
     s->cur = 0;
     s->pull = 0;
     return clear_spare_f(s, 1);
@@ -325,10 +367,12 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     else
         s->geom = Geom{p->nx, p->ny, p->nz, s->N};
     s->stream = (hipStream_t)stream;
+    s->half = p->storage == DSM_STORAGE_FP16 ? 1 : 0;
+    s->es = s->half ? 2 : 4;
     char* base = (char*)dev_buf;
     for (int k = 0; k < 2; ++k) {
-        s->d.f[k] = (float*)(base + L.off_f[k]);
-        s->d.g[k] = (float*)(base + L.off_g[k]);
+        s->d.f[k] = base + L.off_f[k];
+        s->d.g[k] = base + L.off_g[k];
     }
     s->d.c1 = (float*)(base + L.off_c1);
     s->d.mask = (uint8_t*)(base + L.off_mask);
@@ -394,7 +438,7 @@ int dsm_init_solid(dsm_sim* s, int n_steps, double beta, double omega, double ta
         if (rc) return rc;
     }
     // freeze C1 = sum of the solid-stage g
-    HIP_TRY(launch_moment(s->p.dim, s->geom, s->d.g[s->cur], s->d.c1, s->pull, s->stream));
+    HIP_TRY(launch_moment(s->p.dim, s->geom, PG(s, s->cur), s->d.c1, s->pull, s->stream));
     if (flags & DSM_SOLID_REMASK) HIP_TRY(launch_remask(s->d.c1, s->d.mask, s->N, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     int rc = check_flag(s);
@@ -470,11 +514,11 @@ int dsm_step_timed(dsm_sim* s, int n, double* step_ms, double* links_ms) {
         const Phys ph = make_phys(s, s->stage);
         const int c = s->cur, o = 1 - s->cur;
         hipError_t r = hipEventRecord(ev[4 * t], s->stream);
-        if (r == hipSuccess && s->pull) r = launch_bounce(s->d.f[c], s->d.links, s->nlinks, s->stream);
+        if (r == hipSuccess && s->pull) r = launch_bounce(PF(s, c), s->d.links, s->nlinks, s->stream);
         if (r == hipSuccess) r = hipEventRecord(ev[4 * t + 1], s->stream);
         if (r == hipSuccess) r = hipEventRecord(ev[4 * t + 2], s->stream);
         if (r == hipSuccess)
-            r = launch_step_fused(s->p.dim, s->geom, ph, s->d.f[c], s->d.g[c], s->d.f[o], s->d.g[o], s->d.c1,
+            r = launch_step_fused(s->p.dim, s->geom, ph, PF(s, c), PG(s, c), PF(s, o), PG(s, o), s->d.c1,
                                   s->d.mask, s->pull, s->d.flag, s->tile_variant, s->tile_planes, s->stream);
         if (r == hipSuccess) r = hipEventRecord(ev[4 * t + 3], s->stream);
         if (r != hipSuccess) {
@@ -568,13 +612,13 @@ int dsm_chemical_potential(dsm_sim* s, double* mu) {
 int dsm_get_populations(dsm_sim* s, double* f, double* g) {
     if (!s) return fail(DSM_EINVAL, "sim is NULL");
     if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
-    const float* fs = s->d.f[s->cur];
-    const float* gs = s->d.g[s->cur];
+    const void* fs = s->d.f[s->cur];
+    const void* gs = s->d.g[s->cur];
     if (s->pull) {
         const Phys ph = make_phys(s, s->stage);
         const int o = 1 - s->cur;  // the spare pair is free between steps
-        HIP_TRY(launch_pull_state(s->p.dim, s->geom, ph, s->d.f[s->cur], s->d.g[s->cur], s->d.c1, s->d.f[o],
-                                  s->d.g[o], s->stream));
+        HIP_TRY(launch_pull_state(s->p.dim, s->geom, ph, PF(s, s->cur), PG(s, s->cur), s->d.c1, PF(s, o),
+                                  PG(s, o), s->stream));
         fs = s->d.f[o];
         gs = s->d.g[o];
     }
@@ -613,8 +657,8 @@ int dsm_set_postcollision(dsm_sim* s, const double* fs, const double* gs) {
 
 size_t dsm_state_bytes(const dsm_sim* s) {
     if (!s) return 0;
-    const size_t N = (size_t)s->N, Q = (size_t)s->Q;
-    return sizeof(StateHeader) + Q * N * sizeof(float) + g_bytes(s) + N * sizeof(float) + N;
+    const size_t N = (size_t)s->N;
+    return sizeof(StateHeader) + f_bytes(s) + g_bytes(s) + N * sizeof(float) + N;
 }
 
 int dsm_get_state(dsm_sim* s, void* host, size_t bytes) {
@@ -640,9 +684,9 @@ int dsm_get_state(dsm_sim* s, void* host, size_t bytes) {
     char* o = (char*)host;
     memcpy(o, &h, sizeof(h));
     o += sizeof(h);
-    const size_t N = (size_t)s->N, QN = (size_t)s->Q * N;
-    HIP_TRY(hipMemcpyAsync(o, s->d.f[s->cur], QN * sizeof(float), hipMemcpyDeviceToHost, s->stream));
-    o += QN * sizeof(float);
+    const size_t N = (size_t)s->N;
+    HIP_TRY(hipMemcpyAsync(o, s->d.f[s->cur], f_bytes(s), hipMemcpyDeviceToHost, s->stream));
+    o += f_bytes(s);
     HIP_TRY(hipMemcpyAsync(o, s->d.g[s->cur], g_bytes(s), hipMemcpyDeviceToHost, s->stream));
     o += g_bytes(s);
     HIP_TRY(hipMemcpyAsync(o, s->d.c1, N * sizeof(float), hipMemcpyDeviceToHost, s->stream));
@@ -662,16 +706,16 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
         return fail(DSM_EINVAL, "state image is for another lattice");
     if (h.stage != 1 && h.stage != 2) return fail(DSM_EINVAL, "state image has no live stage");
     const char* o = (const char*)host + sizeof(h);
-    const size_t N = (size_t)s->N, QN = (size_t)s->Q * N;
-    HIP_TRY(hipMemcpyAsync(s->d.f[0], o, QN * sizeof(float), hipMemcpyHostToDevice, s->stream));
-    o += QN * sizeof(float);
+    const size_t N = (size_t)s->N;
+    HIP_TRY(hipMemcpyAsync(s->d.f[0], o, f_bytes(s), hipMemcpyHostToDevice, s->stream));
+    o += f_bytes(s);
     HIP_TRY(hipMemcpyAsync(s->d.g[0], o, g_bytes(s), hipMemcpyHostToDevice, s->stream));
     o += g_bytes(s);
     HIP_TRY(hipMemcpyAsync(s->d.c1, o, N * sizeof(float), hipMemcpyHostToDevice, s->stream));
     o += N * sizeof(float);
     HIP_TRY(hipMemcpyAsync(s->d.mask, o, N, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream));
-    HIP_TRY(hipMemsetAsync(s->d.f[1], 0, QN * sizeof(float), s->stream));
+    HIP_TRY(hipMemsetAsync(s->d.f[1], 0, f_bytes(s), s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->cur = 0;
     s->pull = h.pull;

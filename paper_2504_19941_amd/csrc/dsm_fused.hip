@@ -105,25 +105,44 @@ struct Tile {
 constexpr int kRsrcWord3 = 0x00020000;
 constexpr int kNonTemporal = 2;  // cache-policy bit of buffer stores: nt
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, long long plane_floats, int z) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, long long plane_bytes, int z) {
     // the plane start is wave-uniform; saying so keeps the descriptor in SGPRs
-    const unsigned long long a = (unsigned long long)(base + plane_floats * z);
+    const unsigned long long a = (unsigned long long)base + (unsigned long long)(plane_bytes * z);
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
-    float* p = reinterpret_cast<float*>(((unsigned long long)hi << 32) | lo);
-    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)(plane_floats * 4), kRsrcWord3);
-}
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNonTemporal);
+    void* p = reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)plane_bytes, kRsrcWord3);
 }
 
-template <int D, int TXW, int TY, int STAGE, bool PULL>
+// Population element types: loads return the value, stores write it
+// (non-temporal) and return the value as stored, after rounding.
+struct F32 {
+    static constexpr unsigned bytes = 4;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    }
+    static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNonTemporal);
+        return v;
+    }
+};
+struct F16 {  // FP16 holding value * kHalfScale
+    static constexpr unsigned bytes = 2;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+        return __half2float(__ushort_as_half(h)) * (1.f / kHalfScale);
+    }
+    static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+        const __half h = __float2half(v * kHalfScale);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(h), r, (int)voff, (int)soff, kNonTemporal);
+        return __half2float(h) * (1.f / kHalfScale);
+    }
+};
+
+template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
 __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
-    k_step_fused(Geom g, Phys ph, const float* __restrict__ fsrc, const float* __restrict__ gsrc,
-                 float* __restrict__ fdst, float* __restrict__ gdst, const float* __restrict__ c1g,
+    k_step_fused(Geom g, Phys ph, const void* __restrict__ fsrc, const void* __restrict__ gsrc,
+                 void* __restrict__ fdst, void* __restrict__ gdst, const float* __restrict__ c1g,
                  const uint8_t* __restrict__ mask, int* __restrict__ flag, int TZ, int ntx, int nty) {
     using T = Tile<D, TXW, TY>;
     using L = Lattice<D>;
@@ -134,7 +153,8 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 
     const int X = g.X, Y = g.Y, Z = g.Z;
     const int QX = Q * X;                          // floats per row of populations
-    const long long PL = (long long)QX * Y;        // floats per plane of populations
+    const long long PL = (long long)QX * Y * E::bytes;  // bytes per plane of populations
+    constexpr unsigned ES = E::bytes;
 
     // XCD-aware tile order: hardware dispatch is round-robin over the 8 XCDs,
     // so XCD k (= blockIdx % 8) is given a contiguous range of tiles
@@ -158,7 +178,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
     // Own column, wrapped (lanes beyond the lattice edge of a ragged tile
     // compute C of the wrapped column: the last real column needs it).
     const int xv[3] = {pmod(x - 1, X), pmod(x, X), pmod(x + 1, X)};   // x-1, x, x+1
-    const unsigned xb[3] = {4u * xv[0], 4u * xv[1], 4u * xv[2]};         // as byte offsets
+    const unsigned xb[3] = {ES * xv[0], ES * xv[1], ES * xv[2]};         // as byte offsets
     const int yw = pmod(y, Y);
     const int yv[3] = {yw == 0 ? Y - 1 : yw - 1, yw, yw + 1 == Y ? 0 : yw + 1};
 
@@ -178,8 +198,8 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 
     const float fpref3 = 3.f * ph.fpref;
     const float k13 = ph.k1 + ph.k3;
-    const double* __restrict__ g0src = rest_plane(gsrc, Q, g.N);
-    double* __restrict__ g0dst = rest_plane(gdst, Q, g.N);
+    const double* __restrict__ g0src = rest_plane(gsrc, Q, g.N, ES);
+    double* __restrict__ g0dst = rest_plane(gdst, Q, g.N, ES);
     float gA[Q], gB[Q];
 
     auto iteration = [&](int j, float (&gload)[Q], float (&gcoll)[Q], double& cload, double& ccoll) {
@@ -203,7 +223,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                gload[i] = bload(gl[sz], xb[sx], 4u * (unsigned)(yv[sy] * QX + i * X));
+                gload[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * X));
             }
             double acc = 0.0;
 #pragma unroll
@@ -220,7 +240,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                h[i] = bload(gl[sz], xb[sx], 4u * (unsigned)(hyv[sy] * QX + i * X));
+                h[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(hyv[sy] * QX + i * X));
             }
             double acc = 0.0;
 #pragma unroll
@@ -234,7 +254,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                h[i] = bload(gl[sz], 4u * (unsigned)(syv[sy] * QX + i * X + sxv[sx]), 0u);
+                h[i] = E::load(gl[sz], ES * (unsigned)(syv[sy] * QX + i * X + sxv[sx]), 0u);
             }
             double acc = 0.0;
 #pragma unroll
@@ -252,7 +272,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                f[i] = bload(fc[sz], xb[sx], 4u * (unsigned)(yv[sy] * QX + i * X));
+                f[i] = E::load(fc[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * X));
             }
         }
         __syncthreads();
@@ -322,7 +342,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
             uz = mz + 0.5f * Fz;
         }
         const float uu = ux * ux + uy * uy + uz * uz;
-        const unsigned own_off = 4u * (unsigned)(yv[1] * QX);
+        const unsigned own_off = ES * (unsigned)(yv[1] * QX);
         if (!solid) {
             const __amdgpu_buffer_rsrc_t fo = plane_rsrc(fdst, PL, c);
 #pragma unroll
@@ -330,8 +350,8 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
                 const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
                 const float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
                 const float feq = L::w[i] * (pt + s_i(cu, uu));
-                bstore_nt(fo, xb[1], own_off + 4u * (unsigned)(i * X),
-                          f[i] - (f[i] - feq) * ph.inv_tau + fpref3 * L::w[i] * cF);
+                E::store(fo, xb[1], own_off + ES * (unsigned)(i * X),
+                         f[i] - (f[i] - feq) * ph.inv_tau + fpref3 * L::w[i] * cF);
             }
         }
         const __amdgpu_buffer_rsrc_t go = plane_rsrc(gdst, PL, c);
@@ -343,8 +363,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
             const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
             const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
             const float gs = gcoll[i] - (gcoll[i] - geq) * ph.inv_taug;
-            moved += (double)gs;
-            bstore_nt(go, xb[1], own_off + 4u * (unsigned)(i * X), gs);
+            moved += (double)E::store(go, xb[1], own_off + ES * (unsigned)(i * X), gs);
         }
         __builtin_nontemporal_store(ccoll - moved, g0dst + (xv[1] + X * ((long long)yv[1] + (long long)Y * c)));
         if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
@@ -358,38 +377,45 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
     }
 }
 
-template <int D, int TXW, int TY, int STAGE, bool PULL>
-hipError_t launch_cfg(const Geom& g, const Phys& ph, const float* fsrc, const float* gsrc, float* fdst,
-                      float* gdst, const float* c1, const uint8_t* mask, int* flag, int TZ, hipStream_t st) {
+template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
+hipError_t launch_cfg(const Geom& g, const Phys& ph, const void* fsrc, const void* gsrc, void* fdst, void* gdst,
+                      const float* c1, const uint8_t* mask, int* flag, int TZ, hipStream_t st) {
     constexpr int TX = 64 * TXW;
     const int ntx = (g.X + TX - 1) / TX;
     const int nty = (g.Y + TY - 1) / TY;
     const int ntz = (g.Z + TZ - 1) / TZ;
     const long long nblocks = (long long)ntx * nty * ntz;
     if (nblocks < 1 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step_fused<D, TXW, TY, STAGE, PULL>), dim3((unsigned)nblocks), dim3(64 * TXW * TY), 0,
+    hipLaunchKernelGGL((k_step_fused<D, TXW, TY, STAGE, PULL, E>), dim3((unsigned)nblocks), dim3(64 * TXW * TY), 0,
                        st, g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, ntx, nty);
     return hipGetLastError();
 }
 
-template <int D, int TXW, int TY>
-hipError_t launch_tile(const Geom& g, const Phys& ph, const float* fsrc, const float* gsrc, float* fdst,
-                       float* gdst, const float* c1, const uint8_t* mask, int pull, int* flag, int TZ,
-                       hipStream_t st) {
+template <int D, int TXW, int TY, typename E>
+hipError_t launch_tile_e(const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst, const float* c1,
+                         const uint8_t* mask, int pull, int* flag, int TZ, hipStream_t st) {
     if (ph.stage == 2) {
-        if (pull) return launch_cfg<D, TXW, TY, 2, true>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
-        return launch_cfg<D, TXW, TY, 2, false>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
+        if (pull)
+            return launch_cfg<D, TXW, TY, 2, true, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
+        return launch_cfg<D, TXW, TY, 2, false, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
     }
-    if (pull) return launch_cfg<D, TXW, TY, 1, true>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
-    return launch_cfg<D, TXW, TY, 1, false>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, st);
+    if (pull) return launch_cfg<D, TXW, TY, 1, true, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
+    return launch_cfg<D, TXW, TY, 1, false, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
+}
+
+template <int D, int TXW, int TY>
+hipError_t launch_tile(const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst, const float* c1,
+                       const uint8_t* mask, int pull, int* flag, int TZ, hipStream_t st) {
+    if (fsrc.half) return launch_tile_e<D, TXW, TY, F16>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
+    return launch_tile_e<D, TXW, TY, F32>(g, ph, fsrc, gsrc, fdst, gdst, c1, mask, pull, flag, TZ, st);
 }
 
 }  // namespace
 
 int fused_tile_variants(int dim) { return 3; }
 
-hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, const float* fsrc, const float* gsrc,
-                             float* fdst, float* gdst, const float* c1, const uint8_t* mask, int pull, int* flag,
+hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst,
+                             const float* c1, const uint8_t* mask, int pull, int* flag,
                              int variant, int TZ, hipStream_t st) {
     if (TZ < 1) TZ = 1;
     if (dim == 2) {

@@ -32,8 +32,8 @@ struct LinkRec {
 
 // Device arrays of one simulation, carved from the caller's buffer.
 struct DevArrays {
-    float* f[2];      // [Q][N] each
-    float* g[2];      // [Q][N] each
+    void* f[2];       // Q*N population elements each (FP32 or FP16)
+    void* g[2];       // Q*N population elements, then the FP64 rest plane
     float* c1;        // [N]
     uint8_t* mask;    // [N]
     float* phi;       // [N] evolving order parameter (scratch)
@@ -55,21 +55,21 @@ hipError_t launch_c1_from_mask(const uint8_t* mask, float* c1, long long N, hipS
 hipError_t launch_remask(const float* c1, uint8_t* mask, long long N, hipStream_t st);
 hipError_t launch_copy(const float* src, float* dst, long long N, hipStream_t st);
 
-hipError_t launch_moment(int dim, const Geom& g, const float* gsrc, float* phi, int pull, hipStream_t st);
+hipError_t launch_moment(int dim, const Geom& g, Pop gsrc, float* phi, int pull, hipStream_t st);
 hipError_t launch_mu(int dim, const Geom& g, const Phys& ph, const float* phi, const float* c1,
                      const uint8_t* mask, float* mu, hipStream_t st);
-hipError_t launch_collide_split(int dim, const Geom& g, const Phys& ph, const float* fsrc,
-                                const float* gsrc, float* fdst, float* gdst, const float* c1,
+hipError_t launch_collide_split(int dim, const Geom& g, const Phys& ph, Pop fsrc,
+                                Pop gsrc, Pop fdst, Pop gdst, const float* c1,
                                 const float* phi, const float* mu, int pull, int* flag, hipStream_t st);
-hipError_t launch_observe(int dim, const Geom& g, const Phys& ph, const float* fsrc, const float* c1,
+hipError_t launch_observe(int dim, const Geom& g, const Phys& ph, Pop fsrc, const float* c1,
                           const float* phi, const float* mu, int pull, float* aux, hipStream_t st);
 hipError_t launch_init_populations(int dim, const Geom& g, const float* phi, const float* mu,
-                                   float* fdst, float* gdst, hipStream_t st);
-hipError_t launch_pull_state(int dim, const Geom& g, const Phys& ph, const float* fsrc,
-                             const float* gsrc, const float* c1, float* fdst, float* gdst,
+                                   Pop fdst, Pop gdst, hipStream_t st);
+hipError_t launch_pull_state(int dim, const Geom& g, const Phys& ph, Pop fsrc,
+                             Pop gsrc, const float* c1, Pop fdst, Pop gdst,
                              hipStream_t st);
 hipError_t launch_reduce(int dim, const Geom& g, const Phys& ph, const float* c1, const float* phi,
-                         const uint8_t* mask, const float* aux, const float* gsrc, int pull, double* partials,
+                         const uint8_t* mask, const float* aux, Pop gsrc, int pull, double* partials,
                          double* red, hipStream_t st);
 
 // --- interpolated bounce-back (dsm_links.hip) ------------------------------
@@ -80,7 +80,7 @@ hipError_t launch_reduce(int dim, const Geom& g, const Phys& ph, const float* c1
 hipError_t launch_find_links(int dim, const Geom& g, const float* c1, int2* ent, int* count, hipStream_t st);
 hipError_t launch_build_links(int dim, const Geom& g, double alpha, const float* c1, const int2* ent, int nent,
                               LinkRec* rec, long long cap, int* count, hipStream_t st);
-hipError_t launch_bounce(float* f, const LinkRec* rec, int count, hipStream_t st);
+hipError_t launch_bounce(Pop f, const LinkRec* rec, int count, hipStream_t st);
 
 // --- fused step (dsm_fused.hip) ---------------------------------------------
 // variant selects the workgroup tile (3D: 0 = 64x4, 1 = 64x8, 2 = 128x4
@@ -88,9 +88,8 @@ hipError_t launch_bounce(float* f, const LinkRec* rec, int count, hipStream_t st
 // each workgroup marches through.  In the fluid stage with pull != 0 the
 // bounce-back slots of fsrc must have been written by launch_bounce.
 int fused_tile_variants(int dim);
-hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, const float* fsrc,
-                             const float* gsrc, float* fdst, float* gdst, const float* c1,
-                             const uint8_t* mask, int pull, int* flag, int variant, int TZ,
+hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst,
+                             const float* c1, const uint8_t* mask, int pull, int* flag, int variant, int TZ,
                              hipStream_t st);
 
 }  // namespace dsm

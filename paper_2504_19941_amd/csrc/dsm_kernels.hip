@@ -83,7 +83,7 @@ __device__ double link_fraction(const double gc[3], double gnorm, double xi, int
 // linear interpolated bounce-back of Bouzidi et al. where the upstream node
 // is solid (C1 > 1/2).
 template <int D>
-__device__ void pull_f(const Geom& g, const float* fsrc, const float* c1, float alpha, int x, int y,
+__device__ void pull_f(const Geom& g, Pop fsrc, const float* c1, float alpha, int x, int y,
                        int z, long long n, float fout[Lattice<D>::Q]) {
     using L = Lattice<D>;
     unsigned cut = 0;
@@ -95,7 +95,7 @@ __device__ void pull_f(const Geom& g, const float* fsrc, const float* c1, float 
     }
     if (!cut) {
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) fout[i] = fsrc[pop_index(g, L::Q, i, up[i])];
+        for (int i = 0; i < L::Q; ++i) fout[i] = fsrc.ld(pop_index(g, L::Q, i, up[i]));
         return;
     }
     double gc[3] = {0.0, 0.0, 0.0};
@@ -118,20 +118,20 @@ __device__ void pull_f(const Geom& g, const float* fsrc, const float* c1, float 
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         if (!((cut >> i) & 1u)) {
-            fout[i] = fsrc[pop_index(g, L::Q, i, up[i])];
+            fout[i] = fsrc.ld(pop_index(g, L::Q, i, up[i]));
             continue;
         }
         const int k = opp(i);
         double q = link_fraction<D>(gc, gnorm, xi, k);
         long long dn = shifted<D>(g, x, y, z, i, +1);
         bool down_solid = c1[dn] > 0.5f;
-        double fk = (double)fsrc[pop_index(g, L::Q, k, n)];
+        double fk = (double)fsrc.ld(pop_index(g, L::Q, k, n));
         double v;
         if (q < 0.5 && !down_solid) {
-            v = 2.0 * q * fk + (1.0 - 2.0 * q) * (double)fsrc[pop_index(g, L::Q, k, dn)];
+            v = 2.0 * q * fk + (1.0 - 2.0 * q) * (double)fsrc.ld(pop_index(g, L::Q, k, dn));
         } else {
             if (q < 0.5) q = 0.5;
-            v = fk / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * (double)fsrc[pop_index(g, L::Q, i, n)];
+            v = fk / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * (double)fsrc.ld(pop_index(g, L::Q, i, n));
         }
         fout[i] = (float)v;
     }
@@ -156,7 +156,7 @@ __global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, l
 
 // C = sum_i g_i (post-stream g)
 template <int D>
-__global__ void k_moment(Geom g, const float* __restrict__ gsrc, float* __restrict__ phi, int pull) {
+__global__ void k_moment(Geom g, Pop gsrc, float* __restrict__ phi, int pull) {
     using L = Lattice<D>;
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
@@ -166,9 +166,9 @@ __global__ void k_moment(Geom g, const float* __restrict__ gsrc, float* __restri
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
-        acc += (double)gsrc[pop_index(g, L::Q, i, src)];
+        acc += (double)gsrc.ld(pop_index(g, L::Q, i, src));
     }
-    phi[n] = (float)(rest_plane(gsrc, L::Q, g.N)[n] + acc);
+    phi[n] = (float)(gsrc.rest(L::Q, g.N)[n] + acc);
 }
 
 // chemical potential of the fluid stage (mu = dPsi/dC2) or of the solid stage
@@ -205,8 +205,8 @@ __global__ void k_mu(Geom g, Phys ph, const float* __restrict__ phi, const float
 // Mode 0: write post-collision populations to fdst/gdst.
 // Mode 1: write u (dim planes) and the pressure P = p~/3 to aux.
 template <int D, int MODE>
-__global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const float* __restrict__ gsrc,
-                          float* __restrict__ fdst, float* __restrict__ gdst, const float* __restrict__ c1,
+__global__ void k_collide(Geom g, Phys ph, Pop fsrc, Pop gsrc,
+                          Pop fdst, Pop gdst, const float* __restrict__ c1,
                           const float* __restrict__ phi, const float* __restrict__ mu, int pull,
                           int* __restrict__ flag, float* __restrict__ aux) {
     using L = Lattice<D>;
@@ -239,11 +239,11 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
                 pull_f<D>(g, fsrc, c1, ph.alpha, x, y, z, n, f);
             } else {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) f[i] = fsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
+                for (int i = 0; i < Q; ++i) f[i] = fsrc.ld(pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1)));
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) f[i] = fsrc[pop_index(g, L::Q, i, n)];
+            for (int i = 0; i < Q; ++i) f[i] = fsrc.ld(pop_index(g, L::Q, i, n));
         }
         float mx = 0.f, my = 0.f, mz = 0.f;
 #pragma unroll
@@ -272,7 +272,7 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
     const float uu = ux * ux + uy * uy + uz * uz;
     if (solid) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) fdst[pop_index(g, L::Q, i, n)] = 0.f;
+        for (int i = 0; i < Q; ++i) fdst.st(pop_index(g, L::Q, i, n), 0.f);
     } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -280,7 +280,7 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
             float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
             float feq = L::w[i] * (pt + s_i(cu, uu));
             float Fi = ph.fpref * L::w[i] * 3.f * cF;
-            fdst[pop_index(g, L::Q, i, n)] = f[i] - (f[i] - feq) * ph.inv_tau + Fi;
+            fdst.st(pop_index(g, L::Q, i, n), f[i] - (f[i] - feq) * ph.inv_tau + Fi);
         }
     }
     const float m = mu[n];
@@ -289,10 +289,10 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
-        gi[i] = gsrc[pop_index(g, L::Q, i, src)];
+        gi[i] = gsrc.ld(pop_index(g, L::Q, i, src));
         C64 += (double)gi[i];
     }
-    C64 += rest_plane(gsrc, Q, N)[n];
+    C64 += gsrc.rest(Q, N)[n];
     // rest population (FP64) = C - sum of the moving post-collision populations
     double moved = 0.0;
 #pragma unroll
@@ -300,17 +300,16 @@ __global__ void k_collide(Geom g, Phys ph, const float* __restrict__ fsrc, const
         float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
         float geq = L::w[i] * m + L::w[i] * C * s_i(cu, uu);
         float gs = gi[i] - (gi[i] - geq) * ph.inv_taug;
-        moved += (double)gs;
-        gdst[pop_index(g, L::Q, i, n)] = gs;
+        moved += (double)gdst.st(pop_index(g, L::Q, i, n), gs);
     }
-    rest_plane(gdst, Q, N)[n] = C64 - moved;
+    gdst.rest(Q, N)[n] = C64 - moved;
     if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
 }
 
 // t = 0 state: f = 0, g = g_eq(phi, mu, u = 0), as post-stream populations
 template <int D>
 __global__ void k_init_populations(Geom g, const float* __restrict__ phi, const float* __restrict__ mu,
-                                   float* __restrict__ fdst, float* __restrict__ gdst) {
+                                   Pop fdst, Pop gdst) {
     using L = Lattice<D>;
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
@@ -319,19 +318,18 @@ __global__ void k_init_populations(Geom g, const float* __restrict__ phi, const 
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const float geq = L::w[i] * m;
-        moved += (double)geq;
-        gdst[pop_index(g, L::Q, i, n)] = geq;
-        fdst[pop_index(g, L::Q, i, n)] = 0.f;
+        moved += (double)gdst.st(pop_index(g, L::Q, i, n), geq);
+        fdst.st(pop_index(g, L::Q, i, n), 0.f);
     }
-    gdst[pop_index(g, L::Q, 0, n)] = 0.f;  // unused slot: the rest population is FP64
-    rest_plane(gdst, L::Q, g.N)[n] = (double)C - moved;
-    fdst[pop_index(g, L::Q, 0, n)] = 0.f;
+    gdst.st(pop_index(g, L::Q, 0, n), 0.f);  // unused slot: the rest population is FP64
+    gdst.rest(L::Q, g.N)[n] = (double)C - moved;
+    fdst.st(pop_index(g, L::Q, 0, n), 0.f);
 }
 
 // post-collision -> post-stream (with bounce-back for f in the fluid stage)
 template <int D>
-__global__ void k_pull_state(Geom g, Phys ph, const float* __restrict__ fsrc, const float* __restrict__ gsrc,
-                             const float* __restrict__ c1, float* __restrict__ fdst, float* __restrict__ gdst) {
+__global__ void k_pull_state(Geom g, Phys ph, Pop fsrc, Pop gsrc,
+                             const float* __restrict__ c1, Pop fdst, Pop gdst) {
     using L = Lattice<D>;
     constexpr int Q = L::Q;
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -339,9 +337,9 @@ __global__ void k_pull_state(Geom g, Phys ph, const float* __restrict__ fsrc, co
     int x, y, z;
     decode(g, n, x, y, z);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) gdst[pop_index(g, L::Q, i, n)] = gsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
-    gdst[pop_index(g, L::Q, 0, n)] = 0.f;
-    rest_plane(gdst, Q, g.N)[n] = rest_plane(gsrc, Q, g.N)[n];
+    for (int i = 1; i < Q; ++i) gdst.st(pop_index(g, L::Q, i, n), gsrc.ld(pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))));
+    gdst.st(pop_index(g, L::Q, 0, n), 0.f);
+    gdst.rest(Q, g.N)[n] = gsrc.rest(Q, g.N)[n];
     const bool solid = ph.stage == 2 && c1[n] > 0.5f;
     float f[Q];
     if (solid) {
@@ -351,10 +349,10 @@ __global__ void k_pull_state(Geom g, Phys ph, const float* __restrict__ fsrc, co
         pull_f<D>(g, fsrc, c1, ph.alpha, x, y, z, n, f);
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = fsrc[pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))];
+        for (int i = 0; i < Q; ++i) f[i] = fsrc.ld(pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1)));
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fdst[pop_index(g, L::Q, i, n)] = f[i];
+    for (int i = 0; i < Q; ++i) fdst.st(pop_index(g, L::Q, i, n), f[i]);
 }
 
 // --- FP64 reductions -------------------------------------------------------
@@ -377,7 +375,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(Geom g, Phys ph, const float*
                                                    const float* __restrict__ phi,
                                                    const uint8_t* __restrict__ mask,
                                                    const float* __restrict__ aux,
-                                                   const float* __restrict__ gsrc, int pull,
+                                                   Pop gsrc, int pull,
                                                    double* __restrict__ partials) {
     using L = Lattice<D>;
     const long long N = g.N;
@@ -398,10 +396,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce(Geom g, Phys ph, const float*
         double C3 = 1.0 - C1 - C2;
         // masses: the evolving component summed in FP64 from the stored
         // populations themselves, so that drift measures the stored state
-        double cm = rest_plane(gsrc, L::Q, N)[n];
+        double cm = gsrc.rest(L::Q, N)[n];
         for (int i = 1; i < L::Q; ++i) {
             const long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
-            cm += (double)gsrc[pop_index(g, L::Q, i, src)];
+            cm += (double)gsrc.ld(pop_index(g, L::Q, i, src));
         }
         const double m1 = ph.stage == 2 ? C1 : cm, m2 = ph.stage == 2 ? cm : 0.0;
         acc[RED_C1] += m1;
@@ -506,7 +504,7 @@ hipError_t launch_copy(const float* src, float* dst, long long N, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_moment(int dim, const Geom& g, const float* gsrc, float* phi, int pull, hipStream_t st) {
+hipError_t launch_moment(int dim, const Geom& g, Pop gsrc, float* phi, int pull, hipStream_t st) {
     DSM_DISPATCH(dim, k_moment, dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, gsrc, phi, pull);
     return hipGetLastError();
 }
@@ -517,8 +515,8 @@ hipError_t launch_mu(int dim, const Geom& g, const Phys& ph, const float* phi, c
     return hipGetLastError();
 }
 
-hipError_t launch_collide_split(int dim, const Geom& g, const Phys& ph, const float* fsrc,
-                                const float* gsrc, float* fdst, float* gdst, const float* c1,
+hipError_t launch_collide_split(int dim, const Geom& g, const Phys& ph, Pop fsrc,
+                                Pop gsrc, Pop fdst, Pop gdst, const float* c1,
                                 const float* phi, const float* mu, int pull, int* flag, hipStream_t st) {
     if (dim == 2)
         hipLaunchKernelGGL((k_collide<2, 0>), dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, ph, fsrc, gsrc,
@@ -529,34 +527,34 @@ hipError_t launch_collide_split(int dim, const Geom& g, const Phys& ph, const fl
     return hipGetLastError();
 }
 
-hipError_t launch_observe(int dim, const Geom& g, const Phys& ph, const float* fsrc, const float* c1,
+hipError_t launch_observe(int dim, const Geom& g, const Phys& ph, Pop fsrc, const float* c1,
                           const float* phi, const float* mu, int pull, float* aux, hipStream_t st) {
     if (dim == 2)
         hipLaunchKernelGGL((k_collide<2, 1>), dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, ph, fsrc,
-                           (const float*)nullptr, (float*)nullptr, (float*)nullptr, c1, phi, mu, pull,
+                           Pop{nullptr, 0}, Pop{nullptr, 0}, Pop{nullptr, 0}, c1, phi, mu, pull,
                            (int*)nullptr, aux);
     else
         hipLaunchKernelGGL((k_collide<3, 1>), dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, ph, fsrc,
-                           (const float*)nullptr, (float*)nullptr, (float*)nullptr, c1, phi, mu, pull,
+                           Pop{nullptr, 0}, Pop{nullptr, 0}, Pop{nullptr, 0}, c1, phi, mu, pull,
                            (int*)nullptr, aux);
     return hipGetLastError();
 }
 
-hipError_t launch_init_populations(int dim, const Geom& g, const float* phi, const float* mu, float* fdst,
-                                   float* gdst, hipStream_t st) {
+hipError_t launch_init_populations(int dim, const Geom& g, const float* phi, const float* mu, Pop fdst,
+                                   Pop gdst, hipStream_t st) {
     DSM_DISPATCH(dim, k_init_populations, dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, phi, mu, fdst, gdst);
     return hipGetLastError();
 }
 
-hipError_t launch_pull_state(int dim, const Geom& g, const Phys& ph, const float* fsrc, const float* gsrc,
-                             const float* c1, float* fdst, float* gdst, hipStream_t st) {
+hipError_t launch_pull_state(int dim, const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc,
+                             const float* c1, Pop fdst, Pop gdst, hipStream_t st) {
     DSM_DISPATCH(dim, k_pull_state, dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, ph, fsrc, gsrc, c1, fdst,
                  gdst);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(int dim, const Geom& g, const Phys& ph, const float* c1, const float* phi,
-                         const uint8_t* mask, const float* aux, const float* gsrc, int pull, double* partials,
+                         const uint8_t* mask, const float* aux, Pop gsrc, int pull, double* partials,
                          double* red, hipStream_t st) {
     long long want = (g.N + kBlock - 1) / kBlock;
     int blocks = (int)(want < kReduceBlocks ? (want < 1 ? 1 : want) : kReduceBlocks);

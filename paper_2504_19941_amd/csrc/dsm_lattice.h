@@ -11,6 +11,7 @@
 // "planes" along the slowest axis.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -74,21 +75,50 @@ __device__ __forceinline__ long long node_index(const Geom& g, int x, int y, int
 // direction-major, so population i of node n = x + X*row lives at
 // (row*Q + i)*X + x.  A wave reading one direction of one row segment then
 // touches one contiguous run, and a node's Q values sit within Q*X floats.
-// The g populations of one buffer: the Q*N FP32 slots above, of which the
-// moving directions i > 0 are used, followed (256-byte aligned) by the rest
-// population g_0 of every node in FP64, node order.  The rest population
-// carries nearly all of C, so storing it in FP64 keeps the liquid mass from
-// drifting by FP32 rounding at the scale of C (the moving populations are
-// small and their rounding is negligible).
-__host__ __device__ __forceinline__ long long g_float_bytes(int Q, long long N) {
-    return ((long long)Q * N * 4 + 255) / 256 * 256;
+// Population storage.  FP32 (4-byte) or FP16 (2-byte) elements; FP16 holds
+// value * kHalfScale, since the populations of this scheme are deviations
+// from the rest state (f is zero at rest, and the moving g are w_i mu plus
+// advection, both small) whose magnitudes (1e-6 .. 1e-1) would otherwise sit
+// in the subnormal range of FP16.
+constexpr float kHalfScale = 4096.f;
+
+// The g populations of one buffer: the Q*N slots of the population layout,
+// of which the moving directions i > 0 are used, followed (256-byte aligned)
+// by the rest population g_0 of every node in FP64, node order.  The rest
+// population carries nearly all of C, so storing it in FP64 keeps the liquid
+// mass from drifting by rounding at the scale of C (the moving populations
+// are small and their rounding is negligible).
+__host__ __device__ __forceinline__ long long pop_bytes(int Q, long long N, int elem_bytes) {
+    return ((long long)Q * N * elem_bytes + 255) / 256 * 256;
 }
-__host__ __device__ __forceinline__ double* rest_plane(float* g, int Q, long long N) {
-    return reinterpret_cast<double*>(reinterpret_cast<char*>(g) + g_float_bytes(Q, N));
+__host__ __device__ __forceinline__ double* rest_plane(void* g, int Q, long long N, int elem_bytes) {
+    return reinterpret_cast<double*>(reinterpret_cast<char*>(g) + pop_bytes(Q, N, elem_bytes));
 }
-__host__ __device__ __forceinline__ const double* rest_plane(const float* g, int Q, long long N) {
-    return reinterpret_cast<const double*>(reinterpret_cast<const char*>(g) + g_float_bytes(Q, N));
+__host__ __device__ __forceinline__ const double* rest_plane(const void* g, int Q, long long N, int elem_bytes) {
+    return reinterpret_cast<const double*>(reinterpret_cast<const char*>(g) + pop_bytes(Q, N, elem_bytes));
 }
+
+// A population buffer as the non-fused kernels see it: element loads and
+// stores in FP32 whatever the storage.
+struct Pop {
+    void* p;
+    int half;  // 0: FP32 elements, 1: FP16 elements holding value * kHalfScale
+    __device__ __forceinline__ float ld(long long k) const {
+        if (half) return __half2float(reinterpret_cast<const __half*>(p)[k]) * (1.f / kHalfScale);
+        return reinterpret_cast<const float*>(p)[k];
+    }
+    // stores v and returns the value as stored (after rounding)
+    __device__ __forceinline__ float st(long long k, float v) const {
+        if (half) {
+            const __half h = __float2half(v * kHalfScale);
+            reinterpret_cast<__half*>(p)[k] = h;
+            return __half2float(h) * (1.f / kHalfScale);
+        }
+        reinterpret_cast<float*>(p)[k] = v;
+        return v;
+    }
+    __device__ __forceinline__ double* rest(int Q, long long N) const { return rest_plane(p, Q, N, half ? 2 : 4); }
+};
 
 __host__ __device__ __forceinline__ long long pop_index(const Geom& g, int Q, int i, long long n) {
     const long long row = n / g.X;

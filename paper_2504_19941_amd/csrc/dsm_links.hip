@@ -138,11 +138,11 @@ __global__ void __launch_bounds__(kBlock) k_build_links(Geom g, double alpha, co
 // Per step: one thread per cut link.  All reads are populations of fluid
 // nodes and all writes go to slots of solid nodes, so the threads are
 // independent and the update runs in place.
-__global__ void __launch_bounds__(kBlock) k_bounce(float* f, const LinkRec* __restrict__ rec, int count) {
+__global__ void __launch_bounds__(kBlock) k_bounce(Pop f, const LinkRec* __restrict__ rec, int count) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= count) return;
     const LinkRec lr = rec[r];
-    f[lr.dst] = lr.ca * f[lr.a] + lr.cb * f[lr.b];
+    f.st(lr.dst, lr.ca * f.ld(lr.a) + lr.cb * f.ld(lr.b));
 }
 
 }  // namespace
@@ -171,7 +171,7 @@ hipError_t launch_build_links(int dim, const Geom& g, double alpha, const float*
     return hipGetLastError();
 }
 
-hipError_t launch_bounce(float* f, const LinkRec* rec, int count, hipStream_t st) {
+hipError_t launch_bounce(Pop f, const LinkRec* rec, int count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_bounce, dim3(blocks), dim3(kBlock), 0, st, f, rec, count);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libdsm.so")
 DSM_OK, DSM_EINVAL, DSM_ENOMEM, DSM_EDEVICE, DSM_EUNSTABLE, DSM_ESTATE = 0, -1, -2, -3, -4, -5
 DSM_SOLID_RESET, DSM_SOLID_REMASK = 1, 2
 DSM_KERNEL_FUSED, DSM_KERNEL_SPLIT = 0, 1
+DSM_STORAGE_FP32, DSM_STORAGE_FP16 = 0, 1
 
 EXPORTED = [
     "dsm_required_bytes", "dsm_create", "dsm_init_solid", "dsm_set_solid_field", "dsm_set_liquid",
@@ -37,7 +38,7 @@ class dsm_params(ctypes.Structure):
         ("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("kappa", ctypes.c_double * 3), ("alpha", ctypes.c_double), ("tau", ctypes.c_double),
         ("mobility", ctypes.c_double), ("gravity", ctypes.c_double * 3),
-        ("reduce_every", ctypes.c_int), ("kernel", ctypes.c_int),
+        ("reduce_every", ctypes.c_int), ("kernel", ctypes.c_int), ("storage", ctypes.c_int),
     ]
 
 
@@ -109,7 +110,7 @@ def _f64(a):
 # one function per C entry point
 
 def make_params(dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
-                reduce_every=0, kernel=DSM_KERNEL_FUSED) -> dsm_params:
+                reduce_every=0, kernel=DSM_KERNEL_FUSED, storage=DSM_STORAGE_FP32) -> dsm_params:
     p = dsm_params()
     p.dim = int(dim)
     p.nx, p.ny = int(shape[0]), int(shape[1])
@@ -118,7 +119,7 @@ def make_params(dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.
     p.alpha, p.tau, p.mobility = float(alpha), float(tau), float(mobility)
     g = list(gravity) + [0.0] * (3 - len(gravity))
     p.gravity[:] = [float(v) for v in g]
-    p.reduce_every, p.kernel = int(reduce_every), int(kernel)
+    p.reduce_every, p.kernel, p.storage = int(reduce_every), int(kernel), int(storage)
     return p
 
 
@@ -253,12 +254,13 @@ class Simulation:
     """A libdsm.so handle together with the torch device buffer it lives in."""
 
     def __init__(self, dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
-                 mask=None, reduce_every=0, kernel=DSM_KERNEL_FUSED, device="cuda:0", stream=None):
+                 mask=None, reduce_every=0, kernel=DSM_KERNEL_FUSED, storage=DSM_STORAGE_FP32, device="cuda:0",
+                 stream=None):
         import torch
 
         self.dim = dim
         self.shape = tuple(shape)
-        self.params = make_params(dim, shape, kappa, alpha, tau, mobility, gravity, reduce_every, kernel)
+        self.params = make_params(dim, shape, kappa, alpha, tau, mobility, gravity, reduce_every, kernel, storage)
         self.N = int(self.params.nx * self.params.ny * self.params.nz)
         self.Q = 9 if dim == 2 else 19
         self.nbytes = dsm_required_bytes(self.params)

@@ -105,3 +105,13 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.dsm_free_energy(None, None, None) == dsm.DSM_EINVAL
     assert lib.dsm_tiling_variants(3) >= 1
     assert lib.dsm_tiling_variants(5) == 0
+
+
+def test_storage_modes_size_the_buffer(lib):
+    p32 = good_params()
+    p16 = good_params(storage=dsm.DSM_STORAGE_FP16)
+    n32, n16 = dsm.dsm_required_bytes(p32), dsm.dsm_required_bytes(p16)
+    N = 32 * 24 * 16
+    # four population buffers of Q planes shrink from 4 to 2 bytes per element
+    assert n32 - n16 >= 4 * 19 * N * 2 - 4 * 256
+    assert dsm.dsm_required_bytes(good_params(storage=3)) == 0

@@ -199,3 +199,67 @@ def test_contact_angle_matches_oracle_and_young(gpu, theta):
     drift = abs(sim.mass()[1] - m0[1]) / m0[1]
     print(f"  liquid mass drift after {done} steps: {drift:.2e}", flush=True)
     assert drift < 1e-9
+
+
+# --- FP16 population storage -------------------------------------------------
+
+@pytest.mark.parametrize("dim,shape", SHAPES_1000)
+def test_fp16_storage_1000_steps(gpu, dim, shape):
+    """Populations stored as FP16 (FP32 arithmetic): concentrations within
+    2e-3 of the FP64 oracle after 1000 steps, and the liquid mass conserved
+    (the FP64 rest population absorbs the rounding of the moving ones)."""
+    mask, C1, C2 = wall_and_particle(dim, shape, seed=61)
+    C1, C2 = f32(W.flat(C1)), f32(W.flat(C2))
+    grav = (1e-5, -2e-6, 0.0) if dim == 2 else (1e-5, 3e-6, -2e-6)
+    sim = dsm.Simulation(dim, shape, KAPPA, gravity=grav, storage=dsm.DSM_STORAGE_FP16)
+    orc = Oracle(dim, shape, KAPPA, gravity=grav, threads=8)
+    for s in (sim, orc):
+        s.set_solid_field(C1)
+        s.set_liquid(C2)
+    m0 = sim.mass()
+    for s in (sim, orc):
+        s.step(1000)
+    fg, fo = sim.fields(), orc.fields()
+    assert report("C2 (fp16 storage)", fg["C2"], fo["C2"]) < 2e-3
+    assert report("u (fp16 storage)", fg["u"], fo["u"]) < 1e-4
+    drift = abs(sim.mass()[1] - m0[1]) / m0[1]
+    print(f"  liquid mass drift {drift:.2e}", flush=True)
+    assert drift < 1e-9
+
+
+def test_fp16_launch_shape_does_not_change_results(gpu):
+    shape = (70, 13, 21)
+    mask, C1, C2 = wall_and_particle(3, shape, seed=71)
+    ref = None
+    for variant in range(dsm.dsm_tiling_variants(3)):
+        for planes in (1, 16):
+            sim = dsm.Simulation(3, shape, KAPPA, gravity=(1e-5, 0.0, 0.0), storage=dsm.DSM_STORAGE_FP16)
+            sim.set_tiling(variant, planes)
+            sim.set_solid_field(W.flat(C1))
+            sim.set_liquid(W.flat(C2))
+            sim.step(30)
+            st = sim.get_state()
+            if ref is None:
+                ref = st
+            assert st == ref, f"variant {variant} planes {planes} differs"
+
+
+@pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
+def test_fp16_contact_angle(gpu, theta):
+    """FP16 storage: the equilibrium angle within 1 degree of the FP64
+    oracle's, at 20k steps and at the end of the stored history."""
+    gold = _golden(theta)
+    hist = {h["step"]: h["theta"] for h in gold["history"]}
+    w = W.config_2d_contact_angle(theta)
+    sim = dsm.Simulation(2, w.shape, w.kappa, tau=w.tau, mobility=w.mobility, reduce_every=10000,
+                         storage=dsm.DSM_STORAGE_FP16)
+    sim.set_solid_field(f32(W.flat(w.C1)))
+    sim.set_liquid(f32(W.flat(w.C2)))
+    done = 0
+    for target in [20000, max(hist)]:
+        sim.step(target - done)
+        done = target
+        fl = sim.fields()
+        th = A.contact_angle(W.unflat(fl["C1"], w.shape), W.unflat(fl["C2"], w.shape), 1, w.wall_level)
+        print(f"  fp16 theta {theta}: step {target}: gpu {th:.3f}, oracle {hist[target]:.3f}", flush=True)
+        assert abs(th - hist[target]) < 1.0
