@@ -164,6 +164,81 @@ def run_storage(dsm, W, w, dev, storage, args, fluid_nodes, solid_nodes):
     }
 
 
+def run_batch(dsm, W, dev, args):
+    """Batched form on many uneven D2Q9 lattices (drops on sinusoidal walls):
+    the same lattices stepped (a) one after another by the single-lattice
+    launches and (b) together by the tuned persistent batch, replayed
+    from a HIP graph.  Both are timed with events over K steps."""
+    import numpy as np
+    import torch
+
+    ws = W.batch_2d_sinusoid(args.batch_count)
+    sims = []
+    fluid = solid = 0
+    for w in ws:
+        s = dsm.Simulation(2, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
+                           gravity=w.gravity, device=dev)
+        s.set_solid_field(f32(W.flat(w.C1)))
+        s.set_liquid(f32(W.flat(w.C2)))
+        s.step(1)
+        ns = int((np.asarray(w.C1, dtype=np.float32) > 0.5).sum())
+        solid += ns
+        fluid += w.nodes - ns
+        sims.append(s)
+        if len(sims) % 128 == 0:
+            print(f"bench.py: batched form: {len(sims)} lattices set up", file=sys.stderr, flush=True)
+    nodes = fluid + solid
+    print(f"bench.py: batched form: {len(sims)} lattices, {nodes} nodes set up", file=sys.stderr, flush=True)
+    stream = sims[0].stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    # (a) one lattice after another
+    for s in sims:
+        s.step(2)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for s in sims:
+        s.step(args.batch_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / args.batch_steps
+    print(f"bench.py: batched form: one lattice at a time {plain_ms:.3f} ms/step", file=sys.stderr, flush=True)
+    # (b) batched
+    batch = dsm.Batch(sims, device=dev)
+    tune_t0 = time.perf_counter()
+    cost2, _ = batch.tune()
+    tune_s = time.perf_counter() - tune_t0
+    batch.step(args.warmup)
+    wall0 = time.perf_counter()
+    ms = batch.step_timed(args.batch_steps)
+    wall = time.perf_counter() - wall0
+    alg = bytes_per_launch(9, 4, fluid, solid)
+    out = {
+        "workload": f"{len(ws)} D2Q9 lattices {W.BATCH_2D_RECIPE}",
+        "nodes": nodes,
+        "fluid_node_fraction": round(fluid / nodes, 4),
+        "value": round(nodes / (ms * 1e-3) / 1e6, 2),
+        "unit": "MLUPS",
+        "ms_per_step": round(ms, 5),
+        "steps": args.batch_steps,
+        "wall_s_timed": round(wall, 4),
+        "hbm_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "algorithmic_bytes": alg,
+        "schedule": batch.schedule(2),
+        "items": batch.items(2),
+        "modelled_cost": round(cost2, 1),
+        "tune_s": round(tune_s, 3),
+        "one_lattice_at_a_time": {"value": round(nodes / (plain_ms * 1e-3) / 1e6, 2), "unit": "MLUPS",
+                                  "ms_per_step": round(plain_ms, 5)},
+        "speedup_vs_one_at_a_time": round(plain_ms / ms, 3),
+    }
+    batch.close()
+    for s in sims:
+        s.close()
+    return out
+
+
 def error_vs_oracle(dsm, W, w, dev, storage, steps, C2_oracle):
     import numpy as np
 
@@ -187,6 +262,9 @@ def main():
     ap.add_argument("--planes", type=int, default=None, help="planes marched per workgroup")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--batch-count", type=int, default=512, help="lattices in the batched-form measurement")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 plain device copies of this size (counter calibration)")
     args = ap.parse_args()
@@ -284,6 +362,8 @@ def main():
         "speedup_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
         "liquid_mass_drift_rel": r16["drift"],
     }
+    if not args.no_batch:
+        out["batched_2d"] = run_batch(dsm, W, dev, args)
     if not args.no_cpu_baseline:
         report, steps, C2o = cpu_baseline(w, args.cpu_seconds)
         out["cpu_baseline"] = report

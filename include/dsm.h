@@ -202,6 +202,79 @@ int dsm_tiling_variants(int dim);
 /* Releases the host handle (the device buffer stays the caller's). */
 int dsm_destroy(dsm_sim* s);
 
+/* ---- Batched form --------------------------------------------------------
+ *
+ * Many independent lattices of uneven sizes (2D and 3D, the same population
+ * storage) advance together: each step is one bounce-back launch over the cut
+ * links of every lattice, then one persistent launch of the fused step per
+ * lattice type, in which every workgroup takes (lattice, tile) work items
+ * from a shared counter until the list is drained.  The launches of one or
+ * two steps are captured once in a HIP graph and replayed.  Each lattice's
+ * result is bit-identical to stepping it alone with dsm_step (the per-node
+ * arithmetic is the same code and does not depend on the tile; Sec. II,
+ * eqns. of the fluid stage).
+ *
+ * Ownership.  The members stay owned by the caller and must outlive the
+ * batch; the batch keeps its tables (descriptors, work items, link runs,
+ * counters) in ONE caller-owned device buffer of dsm_batch_required_bytes()
+ * bytes, 256-byte aligned, and never allocates device memory.  Between
+ * batch calls a member may be used on its own (fields, energies, single
+ * steps); dsm_batch_step picks up each member's current state.
+ *
+ * A member must be in the fluid stage and have taken at least one step since
+ * dsm_set_liquid (its populations are then post-collision values, which is
+ * the form the persistent kernel reads).  Members must be distinct and share
+ * one population storage.  Errors: DSM_EINVAL, DSM_ESTATE, DSM_ENOMEM,
+ * DSM_EDEVICE. */
+typedef struct dsm_batch dsm_batch;
+
+/* Work schedule of one lattice type in a batch. */
+typedef struct dsm_batch_schedule {
+    int variant;       /* workgroup tile, as in dsm_set_tiling */
+    int planes;        /* planes per work item, 1..4096 */
+    int blocks_per_cu; /* persistent workgroups per compute unit; 0 = as many as are resident at once */
+} dsm_batch_schedule;
+
+/* Bytes of the batch's device buffer for these members (0 if invalid). */
+size_t dsm_batch_required_bytes(dsm_sim* const* sims, int count);
+
+/* Builds the batch and its tables on `stream` (synchronises it).  Default
+ * schedules: 3D variant 2 with 16 planes, 2D variant 2 with 32 planes, all
+ * resident workgroups. */
+int dsm_batch_create(dsm_sim* const* sims, int count, void* dev_buf, size_t dev_bytes, void* stream,
+                     dsm_batch** out);
+
+/* Schedule of the dim-dimensional members (dim 2 or 3). */
+int dsm_batch_set_schedule(dsm_batch* b, int dim, const dsm_batch_schedule* sched);
+int dsm_batch_get_schedule(const dsm_batch* b, int dim, dsm_batch_schedule* sched);
+
+/* Autotuner: for each lattice type present, scores every tile variant with
+ * each of the plane counts 8, 16, 32, 64 and 128 by a model of the batched
+ * step over the members' actual shapes (waves per work item, the two fill
+ * planes of every item, the C halo of the tile, the resident workgroups the
+ * dynamic queue keeps busy, the longest single item), and installs the best.
+ * No device work is issued, so the members' states and step counts are
+ * unchanged.  reps must be 0 (timed tuning is not offered).  cost (may be
+ * NULL) receives the modelled cost of the chosen schedule of each type
+ * (index 0: 2D, 1: 3D; 0 where absent), in wave-plane units. */
+int dsm_batch_tune(dsm_batch* b, int reps, double cost[2]);
+
+/* Advances every member by n steps (n >= 0), then synchronises and checks
+ * the members' stability flags: DSM_EUNSTABLE if any member holds
+ * non-finite values (dsm_last_error names the first). */
+int dsm_batch_step(dsm_batch* b, int n);
+
+/* As dsm_batch_step, and reports the mean time per step (HIP events around
+ * the graph launches, on the batch's stream). */
+int dsm_batch_step_timed(dsm_batch* b, int n, double* ms_per_step);
+
+/* Number of members; work items of the current schedules (2D, 3D). */
+int dsm_batch_size(const dsm_batch* b);
+int dsm_batch_items(const dsm_batch* b, int dim);
+
+/* Releases the batch (its device buffer stays the caller's). */
+int dsm_batch_destroy(dsm_batch* b);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* dsm_last_error(void);
 

@@ -10,8 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "dsm.h"
-#include "dsm_internal.h"
+#include "dsm_host.h"
 
 using namespace dsm;
 
@@ -19,10 +18,16 @@ namespace {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const std::string& msg) {
+}  // namespace
+
+int dsm::set_error(int code, const std::string& msg) {
     g_last_error = msg;
     return code;
 }
+
+namespace {
+
+int fail(int code, const std::string& msg) { return set_error(code, msg); }
 
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
@@ -112,30 +117,7 @@ struct StateHeader {
 
 }  // namespace
 
-struct dsm_sim {
-    dsm_params p;
-    int Q;
-    long long N;
-    Geom geom;
-    hipStream_t stream;
-    DevArrays d;
-    int cur;       // buffer pair holding the live state
-    int pull;      // 1: live buffers hold post-collision populations
-    int stage;     // 0: no live state, 1: solid stage live, 2: fluid stage live
-    long long steps;
-    double beta, omega, tau_s, taug_s;
-    int nlinks;        // boundary nodes with cut links (fluid stage)
-    int tile_variant;  // workgroup tile of the fused step
-    int tile_planes;   // planes marched per workgroup
-    int half;      // populations stored in FP16 (value * kHalfScale)
-    int es;        // bytes per population element
-    std::vector<float> stage_buf;  // host staging for conversions
-    std::vector<uint16_t> stage16;
-};
-
-namespace {
-
-Phys make_phys(const dsm_sim* s, int stage) {
+Phys dsm::sim_phys(const dsm_sim* s, int stage) {
     Phys ph;
     ph.k1 = (float)s->p.kappa[0];
     ph.k2 = (float)s->p.kappa[1];
@@ -160,6 +142,10 @@ Phys make_phys(const dsm_sim* s, int stage) {
     ph.stage = stage;
     return ph;
 }
+
+namespace {
+
+Phys make_phys(const dsm_sim* s, int stage) { return sim_phys(s, stage); }
 
 int upload_field(dsm_sim* s, const double* host, float* dev) {
     const size_t N = (size_t)s->N;

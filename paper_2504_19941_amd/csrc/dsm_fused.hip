@@ -139,31 +139,25 @@ struct F16 {  // FP16 holding value * kHalfScale
     }
 };
 
+// One tile of the march: columns [x0, x0 + 64 TXW) x rows [y0, y0 + TY),
+// planes [z0, z0 + TZ) of one lattice.
 template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
-__global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
-    k_step_fused(Geom g, Phys ph, const void* __restrict__ fsrc, const void* __restrict__ gsrc,
-                 void* __restrict__ fdst, void* __restrict__ gdst, const float* __restrict__ c1g,
-                 const uint8_t* __restrict__ mask, int* __restrict__ flag, int TZ, int ntx, int nty) {
+__device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const void* __restrict__ fsrc,
+                                           const void* __restrict__ gsrc, void* __restrict__ fdst,
+                                           void* __restrict__ gdst, const float* __restrict__ c1g,
+                                           const uint8_t* __restrict__ mask, int* __restrict__ flag, int x0,
+                                           int y0, int z0, int TZ) {
     using T = Tile<D, TXW, TY>;
     using L = Lattice<D>;
     constexpr int Q = L::Q;
-    constexpr int TX = T::TX, CRX = T::CRX, CR = T::CR, HY = T::HY;
+    constexpr int CRX = T::CRX, CR = T::CR, HY = T::HY;
     __shared__ float s_c[4][CR];                                    // C of planes l-3..l (ring)
     __shared__ float s_c1[STAGE == 2 ? 4 : 1][STAGE == 2 ? CR : 1];  // frozen C1, same ring
 
     const int X = g.X, Y = g.Y, Z = g.Z;
-    const int QX = Q * X;                          // floats per row of populations
+    const int QX = Q * X;                               // elements per row of populations
     const long long PL = (long long)QX * Y * E::bytes;  // bytes per plane of populations
     constexpr unsigned ES = E::bytes;
-
-    // XCD-aware tile order: hardware dispatch is round-robin over the 8 XCDs,
-    // so XCD k (= blockIdx % 8) is given a contiguous range of tiles
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
-    const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
-    const int tile_x = tile % ntx, rest = tile / ntx;
-    const int tile_y = rest % nty, tile_z = rest / nty;
-    const int x0 = tile_x * TX, y0 = tile_y * TY, z0 = tile_z * TZ;
     const int zlen = min(TZ, Z - z0);
 
     const int t = threadIdx.x;
@@ -378,6 +372,48 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 }
 
 template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
+__global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
+    k_step_fused(Geom g, Phys ph, const void* __restrict__ fsrc, const void* __restrict__ gsrc,
+                 void* __restrict__ fdst, void* __restrict__ gdst, const float* __restrict__ c1g,
+                 const uint8_t* __restrict__ mask, int* __restrict__ flag, int TZ, int ntx, int nty) {
+    constexpr int TX = 64 * TXW;
+    // XCD-aware tile order: hardware dispatch is round-robin over the 8 XCDs,
+    // so XCD k (= blockIdx % 8) is given a contiguous range of tiles
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
+    const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
+    const int tile_x = tile % ntx, rest = tile / ntx;
+    const int tile_y = rest % nty, tile_z = rest / nty;
+    fused_tile<D, TXW, TY, STAGE, PULL, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, tile_x * TX, tile_y * TY,
+                                           tile_z * TZ, TZ);
+}
+
+// Batched step: many lattices (same lattice type and storage) advance in one
+// persistent launch.  The work list holds (lattice, tile) items, costliest
+// first; each workgroup takes the next item from a shared counter (reset to
+// zero by the bounce kernel that precedes every batched step) until the list
+// is drained, so uneven lattices balance over the chip.  Each lattice's
+// geometry, parameters and buffers come from a descriptor table, with the
+// two buffer pairs exchanged by the step parity.
+template <int D, int TXW, int TY, typename E>
+__global__ void __launch_bounds__(64 * TXW * TY)
+    k_step_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems,
+                 int* __restrict__ counter, int parity, int TZ) {
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();  // also: every wave has left the previous item
+        const int it = s_item;
+        if (it >= nitems) break;  // uniform over the workgroup
+        const BatchItem w = items[it];
+        const BatchInst& d = inst[w.inst];
+        fused_tile<D, TXW, TY, 2, true, E>(d.geom, d.phys, d.f[parity], d.g[parity], d.f[1 - parity],
+                                           d.g[1 - parity], d.c1, d.mask, d.flag, w.x0, w.y0, w.z0, TZ);
+        __syncthreads();  // s_item is rewritten only after every wave has read it
+    }
+}
+
+template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
 hipError_t launch_cfg(const Geom& g, const Phys& ph, const void* fsrc, const void* gsrc, void* fdst, void* gdst,
                       const float* c1, const uint8_t* mask, int* flag, int TZ, hipStream_t st) {
     constexpr int TX = 64 * TXW;
@@ -412,7 +448,76 @@ hipError_t launch_tile(const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fd
 
 }  // namespace
 
+template <int D, int TXW, int TY, typename E>
+auto batch_kernel() {
+    return k_step_batch<D, TXW, TY, E>;
+}
+
+template <int D, int TXW, int TY>
+hipError_t launch_batch_tile(const BatchInst* inst, const BatchItem* items, int nitems, int* counter, int grid,
+                             int parity, int TZ, int half, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = grid < nitems ? grid : nitems;
+    if (half)
+        hipLaunchKernelGGL((k_step_batch<D, TXW, TY, F16>), dim3(blocks), dim3(64 * TXW * TY), 0, st, inst, items,
+                           nitems, counter, parity, TZ);
+    else
+        hipLaunchKernelGGL((k_step_batch<D, TXW, TY, F32>), dim3(blocks), dim3(64 * TXW * TY), 0, st, inst, items,
+                           nitems, counter, parity, TZ);
+    return hipGetLastError();
+}
+
+template <int D, int TXW, int TY>
+int batch_occupancy_tile(int half) {
+    int n = 0;
+    hipError_t e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<D, TXW, TY, F16>(),
+                                                                      64 * TXW * TY, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<D, TXW, TY, F32>(),
+                                                                      64 * TXW * TY, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
 int fused_tile_variants(int dim) { return 3; }
+
+void fused_tile_shape(int dim, int variant, int* tx, int* ty) {
+    static const int t2[3][2] = {{256, 1}, {128, 1}, {64, 1}};
+    static const int t3[3][2] = {{64, 4}, {64, 8}, {128, 4}};
+    const int v = variant < 0 || variant > 2 ? 0 : variant;
+    *tx = dim == 2 ? t2[v][0] : t3[v][0];
+    *ty = dim == 2 ? t2[v][1] : t3[v][1];
+}
+
+hipError_t launch_step_batch(int dim, int variant, int half, const BatchInst* inst, const BatchItem* items,
+                             int nitems, int* counter, int grid, int parity, int TZ, hipStream_t st) {
+    if (TZ < 1) TZ = 1;
+    if (dim == 2) {
+        switch (variant) {
+            case 1: return launch_batch_tile<2, 2, 1>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+            case 2: return launch_batch_tile<2, 1, 1>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+            default: return launch_batch_tile<2, 4, 1>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+        }
+    }
+    switch (variant) {
+        case 1: return launch_batch_tile<3, 1, 8>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+        case 2: return launch_batch_tile<3, 2, 4>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+        default: return launch_batch_tile<3, 1, 4>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+    }
+}
+
+int batch_blocks_per_cu(int dim, int variant, int half) {
+    if (dim == 2) {
+        switch (variant) {
+            case 1: return batch_occupancy_tile<2, 2, 1>(half);
+            case 2: return batch_occupancy_tile<2, 1, 1>(half);
+            default: return batch_occupancy_tile<2, 4, 1>(half);
+        }
+    }
+    switch (variant) {
+        case 1: return batch_occupancy_tile<3, 1, 8>(half);
+        case 2: return batch_occupancy_tile<3, 2, 4>(half);
+        default: return batch_occupancy_tile<3, 1, 4>(half);
+    }
+}
 
 hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst,
                              const float* c1, const uint8_t* mask, int pull, int* flag,

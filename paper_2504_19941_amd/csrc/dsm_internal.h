@@ -30,6 +30,31 @@ struct LinkRec {
     float ca, cb;
 };
 
+// One lattice of a batch as the batched step kernel sees it (the buffer
+// pairs f[k], g[k] alternate with the step parity).
+struct BatchInst {
+    Geom geom;
+    Phys phys;
+    void* f[2];
+    void* g[2];
+    const float* c1;
+    const uint8_t* mask;
+    int* flag;
+    const LinkRec* links;
+    int nlinks;
+    int half;
+};
+// One work item of the batched step: a tile of one lattice.
+struct BatchItem {
+    int inst, x0, y0, z0;
+};
+// A run of up to kBatchChunk consecutive cut links of one lattice, for the
+// batched bounce-back.
+constexpr int kBatchChunk = 256;
+struct BatchChunk {
+    int inst, first;
+};
+
 // Device arrays of one simulation, carved from the caller's buffer.
 struct DevArrays {
     void* f[2];       // Q*N population elements each (FP32 or FP16)
@@ -88,6 +113,13 @@ hipError_t launch_bounce(Pop f, const LinkRec* rec, int count, hipStream_t st);
 // each workgroup marches through.  In the fluid stage with pull != 0 the
 // bounce-back slots of fsrc must have been written by launch_bounce.
 int fused_tile_variants(int dim);
+void fused_tile_shape(int dim, int variant, int* tx, int* ty);
+hipError_t launch_step_batch(int dim, int variant, int half, const BatchInst* inst, const BatchItem* items,
+                             int nitems, int* counter, int grid, int parity, int TZ, hipStream_t st);
+int batch_blocks_per_cu(int dim, int variant, int half);
+hipError_t launch_bounce_batch(const BatchInst* inst, const BatchChunk* chunks, int nchunks, int parity,
+                               int* counters, int ncounters, hipStream_t st);
+hipError_t launch_batch_flags(const BatchInst* inst, int count, int* out, hipStream_t st);
 hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst,
                              const float* c1, const uint8_t* mask, int pull, int* flag, int variant, int TZ,
                              hipStream_t st);

@@ -145,7 +145,46 @@ __global__ void __launch_bounds__(kBlock) k_bounce(Pop f, const LinkRec* __restr
     f.st(lr.dst, lr.ca * f.ld(lr.a) + lr.cb * f.ld(lr.b));
 }
 
+// Batched form: one workgroup per run of kBatchChunk links of one lattice.
+// Workgroup 0 also resets the work counters of the batched step kernels that
+// follow it on the stream.
+__global__ void __launch_bounds__(kBatchChunk)
+    k_bounce_batch(const BatchInst* __restrict__ inst, const BatchChunk* __restrict__ chunks, int nchunks,
+                   int parity, int* __restrict__ counters, int ncounters) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < ncounters) counters[threadIdx.x] = 0;
+    if ((int)blockIdx.x >= nchunks) return;
+    const BatchChunk ch = chunks[blockIdx.x];
+    const BatchInst& d = inst[ch.inst];
+    const int r = ch.first + (int)threadIdx.x;
+    if (r >= d.nlinks) return;
+    const LinkRec lr = d.links[r];
+    const Pop f{d.f[parity], d.half};
+    f.st(lr.dst, lr.ca * f.ld(lr.a) + lr.cb * f.ld(lr.b));
+}
+
+// out[k] = flag word of lattice k (non-zero: non-finite values were seen).
+__global__ void __launch_bounds__(kBlock) k_batch_flags(const BatchInst* __restrict__ inst, int count,
+                                                        int* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) out[k] = inst[k].flag[0];
+}
+
 }  // namespace
+
+hipError_t launch_bounce_batch(const BatchInst* inst, const BatchChunk* chunks, int nchunks, int parity,
+                               int* counters, int ncounters, hipStream_t st) {
+    const unsigned blocks = (unsigned)(nchunks > 0 ? nchunks : 1);
+    hipLaunchKernelGGL(k_bounce_batch, dim3(blocks), dim3(kBatchChunk), 0, st, inst, chunks, nchunks, parity,
+                       counters, ncounters);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_flags(const BatchInst* inst, int count, int* out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_batch_flags, dim3(blocks), dim3(kBlock), 0, st, inst, count, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_find_links(int dim, const Geom& g, const float* c1, int2* ent, int* count, hipStream_t st) {
     const unsigned blocks = (unsigned)((g.N + kBlock - 1) / kBlock);

@@ -28,6 +28,9 @@ EXPORTED = [
     "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
     "dsm_state_bytes", "dsm_get_state", "dsm_set_state", "dsm_step_count", "dsm_set_tiling",
     "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
+    "dsm_batch_required_bytes", "dsm_batch_create", "dsm_batch_set_schedule", "dsm_batch_get_schedule",
+    "dsm_batch_tune", "dsm_batch_step", "dsm_batch_step_timed", "dsm_batch_size", "dsm_batch_items",
+    "dsm_batch_destroy",
 ]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -40,6 +43,10 @@ class dsm_params(ctypes.Structure):
         ("mobility", ctypes.c_double), ("gravity", ctypes.c_double * 3),
         ("reduce_every", ctypes.c_int), ("kernel", ctypes.c_int), ("storage", ctypes.c_int),
     ]
+
+
+class dsm_batch_schedule(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int), ("planes", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
 
 
 class DsmError(RuntimeError):
@@ -89,6 +96,19 @@ def load(path: str = LIB_PATH):
     lib.dsm_destroy.argtypes = [vp]
     lib.dsm_last_error.argtypes = []
     lib.dsm_last_error.restype = ctypes.c_char_p
+    vpp = ctypes.POINTER(vp)
+    sp = ctypes.POINTER(dsm_batch_schedule)
+    lib.dsm_batch_required_bytes.argtypes = [vpp, ctypes.c_int]
+    lib.dsm_batch_required_bytes.restype = ctypes.c_size_t
+    lib.dsm_batch_create.argtypes = [vpp, ctypes.c_int, vp, ctypes.c_size_t, vp, vpp]
+    lib.dsm_batch_set_schedule.argtypes = [vp, ctypes.c_int, sp]
+    lib.dsm_batch_get_schedule.argtypes = [vp, ctypes.c_int, sp]
+    lib.dsm_batch_tune.argtypes = [vp, ctypes.c_int, _dp]
+    lib.dsm_batch_step.argtypes = [vp, ctypes.c_int]
+    lib.dsm_batch_step_timed.argtypes = [vp, ctypes.c_int, _dp]
+    lib.dsm_batch_size.argtypes = [vp]
+    lib.dsm_batch_items.argtypes = [vp, ctypes.c_int]
+    lib.dsm_batch_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -248,6 +268,66 @@ def dsm_last_error() -> str:
     return load().dsm_last_error().decode()
 
 
+def _handles(handles):
+    arr = (ctypes.c_void_p * len(handles))()
+    for k, h in enumerate(handles):
+        arr[k] = h.value if isinstance(h, ctypes.c_void_p) else h
+    return arr
+
+
+def dsm_batch_required_bytes(handles) -> int:
+    return int(load().dsm_batch_required_bytes(_handles(handles), len(handles)))
+
+
+def dsm_batch_create(handles, dev_ptr: int, dev_bytes: int, stream: int):
+    h = ctypes.c_void_p()
+    rc = load().dsm_batch_create(_handles(handles), len(handles), ctypes.c_void_p(dev_ptr),
+                                 ctypes.c_size_t(dev_bytes), ctypes.c_void_p(stream), ctypes.byref(h))
+    _check(rc, "dsm_batch_create")
+    return h
+
+
+def dsm_batch_set_schedule(b, dim, variant, planes, blocks_per_cu=0):
+    s = dsm_batch_schedule(int(variant), int(planes), int(blocks_per_cu))
+    _check(load().dsm_batch_set_schedule(b, int(dim), ctypes.byref(s)), "dsm_batch_set_schedule")
+
+
+def dsm_batch_get_schedule(b, dim):
+    s = dsm_batch_schedule()
+    _check(load().dsm_batch_get_schedule(b, int(dim), ctypes.byref(s)), "dsm_batch_get_schedule")
+    return {"variant": s.variant, "planes": s.planes, "blocks_per_cu": s.blocks_per_cu}
+
+
+def dsm_batch_tune(b, reps=0):
+    """Installs the modelled best schedules; returns their modelled costs
+    (2D, 3D) in wave-plane units."""
+    t = np.zeros(2)
+    _check(load().dsm_batch_tune(b, int(reps), _p(t)), "dsm_batch_tune")
+    return float(t[0]), float(t[1])
+
+
+def dsm_batch_step(b, n):
+    _check(load().dsm_batch_step(b, int(n)), "dsm_batch_step")
+
+
+def dsm_batch_step_timed(b, n) -> float:
+    ms = ctypes.c_double()
+    _check(load().dsm_batch_step_timed(b, int(n), ctypes.byref(ms)), "dsm_batch_step_timed")
+    return ms.value
+
+
+def dsm_batch_size(b) -> int:
+    return int(load().dsm_batch_size(b))
+
+
+def dsm_batch_items(b, dim) -> int:
+    return int(load().dsm_batch_items(b, int(dim)))
+
+
+def dsm_batch_destroy(b):
+    _check(load().dsm_batch_destroy(b), "dsm_batch_destroy")
+
+
 # ---------------------------------------------------------------------------
 
 class Simulation:
@@ -336,3 +416,56 @@ class Simulation:
     @property
     def steps(self) -> int:
         return dsm_step_count(self.handle)
+
+
+class Batch:
+    """A libdsm.so batch over Simulation objects, with its torch device buffer.
+
+    The Simulations must stay alive while the batch exists."""
+
+    def __init__(self, sims, device="cuda:0", stream=None):
+        import torch
+
+        self.sims = list(sims)
+        handles = [s.handle for s in self.sims]
+        self.nbytes = dsm_batch_required_bytes(handles)
+        if self.nbytes == 0:
+            raise DsmError(DSM_EINVAL, "dsm_batch_required_bytes", "invalid members")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self.buffer.data_ptr() + 255) // 256 * 256
+        self.handle = dsm_batch_create(handles, base, self.nbytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            dsm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_schedule(self, dim, variant, planes, blocks_per_cu=0):
+        dsm_batch_set_schedule(self.handle, dim, variant, planes, blocks_per_cu)
+
+    def schedule(self, dim):
+        return dsm_batch_get_schedule(self.handle, dim)
+
+    def tune(self, reps=0):
+        return dsm_batch_tune(self.handle, reps)
+
+    def step(self, n):
+        dsm_batch_step(self.handle, n)
+
+    def step_timed(self, n):
+        return dsm_batch_step_timed(self.handle, n)
+
+    def items(self, dim):
+        return dsm_batch_items(self.handle, dim)
+
+    @property
+    def nodes(self) -> int:
+        return sum(s.N for s in self.sims)

@@ -195,6 +195,54 @@ def sinusoid_mask(shape, amplitude: float, wavelength: float, base: float) -> np
     return (Y <= ys).astype(np.uint8)
 
 
+def sinusoid_surface(shape, amplitude: float, wavelength: float, base: float, alpha: float = 1.0):
+    """2D diffuse solid below y_s(x) = base + A sin(2 pi x / lambda): C1 is
+    the tanh profile of the signed distance to the surface, taken to first
+    order as (y_s(x) - y) / sqrt(1 + y_s'(x)^2); the mask is C1 > 1/2."""
+    X, Y = _coords(shape)
+    k = 2.0 * np.pi / wavelength
+    ys = base + amplitude * np.sin(k * X)
+    slope = amplitude * k * np.cos(k * X)
+    d = (ys - Y) / np.sqrt(1.0 + slope ** 2)
+    C1 = tanh_profile(d, alpha)
+    return (C1 > 0.5).astype(np.uint8), C1
+
+
+BATCH_2D_RECIPE = ("(nx 64-512, ny 32-256; sinusoidal walls A 2-12, lambda 16-128; drops R 15-40; "
+                   "theta 45-135 deg; body force 1e-7-1e-5)")
+
+
+def batch_2d_sinusoid(count: int = 512, seed: int = 4, size_lo=(64, 32), size_hi=(512, 256)) -> list:
+    """Independent D2Q9 drops on sinusoidally undulated walls, all drawn from
+    one seed: lattice nx in [64, 512] and ny in [32, 256] (uniform integers),
+    amplitude 2-12 nodes, wavelength 16-128 rounded so that a whole number of
+    periods fits the periodic x extent, drop radius 15-40 clipped to what the
+    lattice holds, contact angle 45-135 degrees, body force 1e-7-1e-5
+    (log-uniform) along x.  The wall's troughs sit 4 nodes above the bottom."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        nx = int(rng.integers(size_lo[0], size_hi[0] + 1))
+        ny = int(rng.integers(size_lo[1], size_hi[1] + 1))
+        amp = float(rng.uniform(2.0, 12.0))
+        lam = float(rng.uniform(16.0, 128.0))
+        lam = nx / max(1, round(nx / lam))
+        base = amp + 4.0
+        radius = float(rng.uniform(15.0, 40.0))
+        radius = max(4.0, min(radius, 0.4 * nx, ny - base - amp - 4.0))
+        theta = float(rng.uniform(45.0, 135.0))
+        g = float(10.0 ** rng.uniform(-7.0, -5.0))
+        shape = (nx, ny)
+        mask, C1 = sinusoid_surface(shape, amp, lam, base)
+        xc = 0.5 * nx
+        yc = base + amp * np.sin(2.0 * np.pi * xc / lam)
+        C2 = drop_field(shape, (xc, yc), radius, C1, open_axis=1)
+        out.append(Workload(name=f"d2q9-{nx}x{ny}-sin{amp:.1f}x{lam:.1f}-R{radius:.1f}-theta{theta:.0f}",
+                            dim=2, shape=shape, kappa=kappas_for_angle(theta), mask=mask, C1=C1, C2=C2,
+                            gravity=(g, 0.0, 0.0), seed=seed * 100003 + k))
+    return out
+
+
 def random_postcollision_state(Q: int, shape, C2: np.ndarray, seed: int, amp: float = 1e-3):
     """Seeded random post-collision populations around a liquid field:
     f* = amp * U(-1, 1); g*_0 = C2 + amp * U(-1, 1); g*_i = amp * U(-1, 1)

@@ -115,3 +115,27 @@ def test_storage_modes_size_the_buffer(lib):
     # four population buffers of Q planes shrink from 4 to 2 bytes per element
     assert n32 - n16 >= 4 * 19 * N * 2 - 4 * 256
     assert dsm.dsm_required_bytes(good_params(storage=3)) == 0
+
+
+def test_batch_calls_reject_invalid_arguments_without_a_device(lib):
+    """Batch calls validate their arguments on the host: NULL or empty member
+    lists, NULL handles and NULL outputs never reach the device."""
+    vp = ctypes.c_void_p
+    arr = (vp * 2)()
+    assert lib.dsm_batch_required_bytes(None, 3) == 0
+    assert lib.dsm_batch_required_bytes(arr, 0) == 0
+    assert lib.dsm_batch_required_bytes(arr, 2) == 0  # NULL members
+    out = vp()
+    assert lib.dsm_batch_create(arr, 2, vp(1 << 20), 1 << 20, None, None) == dsm.DSM_EINVAL
+    assert lib.dsm_batch_create(arr, 2, vp(1 << 20), 1 << 20, None, ctypes.byref(out)) == dsm.DSM_EINVAL
+    assert out.value is None
+    assert "NULL" in dsm.dsm_last_error()
+    s = dsm.dsm_batch_schedule(0, 16, 0)
+    assert lib.dsm_batch_set_schedule(None, 2, ctypes.byref(s)) == dsm.DSM_EINVAL
+    assert lib.dsm_batch_get_schedule(None, 2, ctypes.byref(s)) == dsm.DSM_EINVAL
+    assert lib.dsm_batch_tune(None, 2, None) == dsm.DSM_EINVAL
+    assert lib.dsm_batch_step(None, 1) == dsm.DSM_EINVAL
+    assert lib.dsm_batch_step_timed(None, 1, None) == dsm.DSM_EINVAL
+    assert lib.dsm_batch_size(None) == -1
+    assert lib.dsm_batch_items(None, 2) == -1
+    assert lib.dsm_batch_destroy(None) == dsm.DSM_EINVAL
