@@ -239,6 +239,39 @@ def run_batch(dsm, W, dev, args):
     return out
 
 
+def run_serve(dsm, W, dev, args, plain_mlups):
+    """Served form: a Poisson stream of 3D jobs of two kinds admitted by
+    footprint into one device arena and advanced together in quanta by the
+    batched step; latency is arrival to result on the host clock (admission
+    set-up, the steps, and the copy of the result included)."""
+    from paper_2504_19941_amd import serve as S
+
+    pairs = W.serve_jobs(args.serve_jobs, seed=5, steps=(200, 1000))
+    jobs = [S.Job(k, w, n, storage=dsm.DSM_STORAGE_FP16 if k % 4 == 3 else dsm.DSM_STORAGE_FP32)
+            for k, (w, n) in enumerate(pairs)]
+    mean_work = sum(j.nodes * j.steps for j in jobs) / len(jobs)
+    rate = args.serve_load * args.serve_capacity_lups / mean_work
+    arrivals = S.poisson_arrivals(len(jobs), rate, seed=6)
+    cap = int(args.serve_gib * (1 << 30))
+    srv = S.make_gpu_server(cap, quantum=args.serve_quantum, device=dev)
+    print(f"bench.py: served form: {len(jobs)} jobs, {rate:.2f} arrivals/s, arena {args.serve_gib} GiB",
+          file=sys.stderr, flush=True)
+    elapsed = S.run_stream(srv, jobs, arrivals)
+    rep = S.report(jobs, elapsed)
+    rep.update({
+        "workload": W.SERVE_RECIPE + f"; steps 200-1000; every 4th job FP16 storage",
+        "arrival_rate_per_s": round(rate, 3),
+        "offered_load": args.serve_load,
+        "arena_GiB": args.serve_gib,
+        "quantum_steps": args.serve_quantum,
+        "peak_arena_GiB": round(srv.arena.peak / (1 << 30), 3),
+        "rounds": srv.rounds,
+        "unit": "s (latency), MLUPS (aggregate)",
+        "aggregate_vs_plain_fp32_128cube": round(rep["aggregate_mlups"] / plain_mlups, 3),
+    })
+    return rep
+
+
 def error_vs_oracle(dsm, W, w, dev, storage, steps, C2_oracle):
     import numpy as np
 
@@ -265,6 +298,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--batch-count", type=int, default=512, help="lattices in the batched-form measurement")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--serve-jobs", type=int, default=48)
+    ap.add_argument("--serve-gib", type=float, default=16.0, help="device arena of the served form")
+    ap.add_argument("--serve-quantum", type=int, default=50, help="steps per round of the served form")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="offered load: arrival rate x mean job work / --serve-capacity-lups")
+    ap.add_argument("--serve-capacity-lups", type=float, default=12e9)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 plain device copies of this size (counter calibration)")
     args = ap.parse_args()
@@ -364,6 +404,8 @@ def main():
     }
     if not args.no_batch:
         out["batched_2d"] = run_batch(dsm, W, dev, args)
+    if not args.no_serve:
+        out["served_3d"] = run_serve(dsm, W, dev, args, mlups)
     if not args.no_cpu_baseline:
         report, steps, C2o = cpu_baseline(w, args.cpu_seconds)
         out["cpu_baseline"] = report

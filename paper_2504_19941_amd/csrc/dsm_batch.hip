@@ -300,31 +300,36 @@ int check_sched(int dim, const dsm_batch_schedule* s) {
 // Plane counts the tuner considers.
 constexpr int kTunePlanes[] = {8, 16, 32, 64, 128};
 
+// Relative cost of one wave marching one plane, per tile variant (index:
+// variant).  Measured on MI355X with the batched kernel: a wave of a wider
+// tile is cheaper, because the tile's workgroup shares the C halo and the
+// barrier of each plane among more waves (2D: 256/128/64 columns; 3D:
+// 64x4/64x8/128x4 columns).
+constexpr double kWaveCost[2][3] = {{1.0, 1.35, 1.58}, {1.08, 1.06, 1.0}};
+
 // Modelled duration of one batched step of the members of one lattice type
 // under a schedule, in units of one wave marching one plane.  A wave costs
-// the same whether or not all of its lanes hold lattice columns, each work
-// item marches two planes beyond its own (the planes that fill the C ring
-// before the first collision), and each plane of an item also reads the C
-// halo around the tile (charged by its cells relative to the tile's).  The
-// dynamic work queue keeps every resident workgroup busy until the list is
-// drained, so the step lasts the larger of the total work spread over the
-// resident waves and the longest single item.
-double schedule_cost(const dsm_batch* b, int dim, int tx, int ty, int planes, int per_cu) {
+// the same whether or not all of its lanes hold lattice columns, and each
+// work item marches two planes beyond its own (the planes that fill the C
+// ring before the first collision).  The dynamic queue, fed costliest item
+// first, keeps every resident wave busy until the list is drained, so the
+// step lasts the total work over the resident waves plus a tail charged at
+// a quarter of the longest item.
+double schedule_cost(const dsm_batch* b, int dim, int variant, int planes, int per_cu) {
+    int tx = 0, ty = 0;
+    fused_tile_shape(dim, variant, &tx, &ty);
     const double waves_per_item = (double)(tx / 64) * ty;
-    const double halo = (double)((tx + 2) * (ty + (dim == 3 ? 2 : 0))) / (double)(tx * ty);
     double total = 0.0, longest = 0.0;
     for (const dsm_sim* m : b->sims) {
         if (m->p.dim != dim) continue;
         const Geom& g = m->geom;
         const double tiles = (double)((g.X + tx - 1) / tx) * (double)((g.Y + ty - 1) / ty);
         const int full = g.Z / planes, tail = g.Z % planes;
-        const double item = (planes + 2) * waves_per_item * halo;
-        total += tiles * full * item;
-        if (tail) total += tiles * (tail + 2) * waves_per_item * halo;
-        longest = std::max(longest, full ? item : (tail + 2) * waves_per_item * halo);
+        total += tiles * waves_per_item * ((double)full * (planes + 2) + (tail ? tail + 2 : 0));
+        longest = std::max(longest, (double)(full ? planes + 2 : tail + 2));
     }
     const double resident_waves = (double)b->cus * per_cu * waves_per_item;
-    return std::max(total / resident_waves, longest);
+    return kWaveCost[dim - 2][variant] * (total / resident_waves + 0.25 * longest);
 }
 
 }  // namespace
@@ -418,11 +423,9 @@ int dsm_batch_tune(dsm_batch* b, int reps, double cost[2]) {
         dsm_batch_schedule best = b->sched[t];
         double best_cost = 1e300;
         for (int v = 0; v < fused_tile_variants(dim); ++v) {
-            int tx = 0, ty = 0;
-            fused_tile_shape(dim, v, &tx, &ty);
             const int per_cu = batch_blocks_per_cu(dim, v, b->half);
             for (int planes : kTunePlanes) {
-                const double c = schedule_cost(b, dim, tx, ty, planes, per_cu);
+                const double c = schedule_cost(b, dim, v, planes, per_cu);
                 if (c < best_cost) {
                     best_cost = c;
                     best = dsm_batch_schedule{v, planes, 0};

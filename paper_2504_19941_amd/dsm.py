@@ -335,7 +335,10 @@ class Simulation:
 
     def __init__(self, dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
                  mask=None, reduce_every=0, kernel=DSM_KERNEL_FUSED, storage=DSM_STORAGE_FP32, device="cuda:0",
-                 stream=None):
+                 stream=None, dev_ptr=None):
+        """dev_ptr: optional 256-byte aligned device address of at least
+        dsm_required_bytes bytes that the caller owns (e.g. a block of a
+        larger arena); by default a torch buffer is allocated."""
         import torch
 
         self.dim = dim
@@ -348,10 +351,13 @@ class Simulation:
             raise DsmError(DSM_EINVAL, "dsm_required_bytes", "invalid parameters")
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        # over-allocate by 256 bytes so the handle's base can be 256-byte aligned
-        self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.buffer.data_ptr()
-        self.base = (base + 255) // 256 * 256
+        if dev_ptr is None:
+            # over-allocate by 256 bytes so the handle's base can be 256-byte aligned
+            self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.base = (self.buffer.data_ptr() + 255) // 256 * 256
+        else:
+            self.buffer = None
+            self.base = int(dev_ptr)
         self.handle = dsm_create(self.params, mask, self.base, self.nbytes, self.stream.cuda_stream)
 
     def close(self):
@@ -423,7 +429,9 @@ class Batch:
 
     The Simulations must stay alive while the batch exists."""
 
-    def __init__(self, sims, device="cuda:0", stream=None):
+    def __init__(self, sims, device="cuda:0", stream=None, dev_ptr=None):
+        """dev_ptr: optional caller-owned 256-byte aligned device address of
+        at least dsm_batch_required_bytes bytes (default: a torch buffer)."""
         import torch
 
         self.sims = list(sims)
@@ -433,8 +441,12 @@ class Batch:
             raise DsmError(DSM_EINVAL, "dsm_batch_required_bytes", "invalid members")
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = (self.buffer.data_ptr() + 255) // 256 * 256
+        if dev_ptr is None:
+            self.buffer = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = (self.buffer.data_ptr() + 255) // 256 * 256
+        else:
+            self.buffer = None
+            base = int(dev_ptr)
         self.handle = dsm_batch_create(handles, base, self.nbytes, self.stream.cuda_stream)
 
     def close(self):

@@ -1,0 +1,380 @@
+"""Served continuous batching of lattice jobs on one GPU.
+
+A request loop keeps the populations of every admitted job resident in one
+device arena.  Queued jobs are admitted first in, first out as soon as the
+arena has room for their exact footprint (``dsm_required_bytes``); resident
+jobs advance together, a quantum of steps at a time, through the batched
+step of libdsm.so (one batch per population storage), so the work of jobs
+that arrived at different times overlaps in the same launches.  A job that
+arrives while others run joins at the next quantum boundary; a quantum never
+runs past the step count any resident job asked for, so each job leaves at
+exactly its own step and its result is the one it would have alone.
+
+The scheduling logic (``Arena``, ``Server``, ``run_stream``) is plain host
+code; device work goes through an executor: ``GpuExecutor`` drives the C ABI,
+``ModelExecutor`` replaces it with a timing model for host-only tests.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+ALIGN = 256
+
+
+class Arena:
+    """First-fit allocator over the byte range [0, capacity): blocks are
+    rounded up to 256 bytes, free neighbours merge."""
+
+    def __init__(self, capacity: int, align: int = ALIGN):
+        self.align = align
+        self.capacity = capacity // align * align
+        self.free_list = [(0, self.capacity)] if self.capacity else []  # (offset, size), by offset
+        self.blocks = {}  # offset -> size
+        self.peak = 0
+
+    @property
+    def used(self) -> int:
+        return sum(self.blocks.values())
+
+    @property
+    def largest_free(self) -> int:
+        return max((s for _, s in self.free_list), default=0)
+
+    def round(self, nbytes: int) -> int:
+        return max(self.align, -(-int(nbytes) // self.align) * self.align)
+
+    def alloc(self, nbytes: int):
+        size = self.round(nbytes)
+        for k, (off, s) in enumerate(self.free_list):
+            if s >= size:
+                if s == size:
+                    del self.free_list[k]
+                else:
+                    self.free_list[k] = (off + size, s - size)
+                self.blocks[off] = size
+                self.peak = max(self.peak, self.used)
+                return off
+        return None
+
+    def free(self, off: int):
+        size = self.blocks.pop(off)
+        fl = self.free_list
+        k = 0
+        while k < len(fl) and fl[k][0] < off:
+            k += 1
+        fl.insert(k, (off, size))
+        if k + 1 < len(fl) and fl[k][0] + fl[k][1] == fl[k + 1][0]:
+            fl[k] = (fl[k][0], fl[k][1] + fl[k + 1][1])
+            del fl[k + 1]
+        if k > 0 and fl[k - 1][0] + fl[k - 1][1] == fl[k][0]:
+            fl[k - 1] = (fl[k - 1][0], fl[k - 1][1] + fl[k][1])
+            del fl[k]
+
+
+@dataclass
+class Job:
+    """One simulation request: a workload (geometry, parameters, initial
+    liquid), the number of fluid steps to run, the population storage."""
+    id: int
+    workload: object
+    steps: int
+    storage: int = 0
+    arrival: float = 0.0
+    nbytes: int = 0
+    offset: int | None = None
+    done_steps: int = 0
+    admitted: float | None = None
+    finished: float | None = None
+    result: dict | None = None
+
+    @property
+    def nodes(self) -> int:
+        return int(np.prod(self.workload.shape))
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    """The request loop's state: queue, arena, resident jobs.  ``step``
+    performs one round: admit what fits, rebuild the batches if the resident
+    set changed, run one quantum, retire the jobs that reached their step
+    count.  Times passed in are seconds on the caller's clock."""
+
+    def __init__(self, executor, capacity: int, quantum: int = 50, table_fraction: float = 1.0 / 256):
+        self.ex = executor
+        tables = max(16 << 20, int(capacity * table_fraction)) // ALIGN * ALIGN
+        if capacity <= tables:
+            raise ValueError("capacity too small")
+        self.arena = Arena(capacity - tables)
+        self.tables = Arena(tables)
+        self.table_blocks = {}
+        self.quantum = int(quantum)
+        self.queue = collections.deque()
+        self.running = []
+        self.done = []
+        self.changed = False
+        self.rounds = 0
+        self.steps_run = 0
+
+    @property
+    def busy(self) -> bool:
+        return bool(self.queue or self.running)
+
+    def submit(self, job: Job, now: float):
+        job.arrival = now
+        job.nbytes = self.ex.job_bytes(job)
+        if self.arena.round(job.nbytes) > self.arena.capacity:
+            raise ValueError(f"job {job.id} needs {job.nbytes} bytes, more than the arena holds")
+        if job.steps < 1:
+            raise ValueError(f"job {job.id}: steps must be >= 1")
+        self.queue.append(job)
+
+    def _admit(self, now: float) -> list:
+        admitted = []
+        while self.queue:
+            job = self.queue[0]
+            off = self.arena.alloc(job.nbytes)
+            if off is None:
+                break  # first in, first out: later jobs wait behind the head
+            self.queue.popleft()
+            job.offset = off
+            job.admitted = now
+            job.done_steps = self.ex.start(job, off)
+            self.running.append(job)
+            admitted.append(job)
+        return admitted
+
+    def _rebuild(self):
+        for off in self.table_blocks.values():
+            self.tables.free(off)
+        self.table_blocks = {}
+        while True:
+            need = self.ex.table_bytes(self.running)
+            blocks = {}
+            ok = True
+            for key, nbytes in need.items():
+                off = self.tables.alloc(nbytes)
+                if off is None:
+                    ok = False
+                    break
+                blocks[key] = off
+            if ok:
+                self.table_blocks = blocks
+                self.ex.rebuild(self.running, blocks)
+                return
+            for off in blocks.values():
+                self.tables.free(off)
+            # the tables of this resident set do not fit: send the newest
+            # job back to the head of the queue
+            job = self.running.pop()
+            self.ex.drop(job)
+            self.arena.free(job.offset)
+            job.offset, job.admitted, job.done_steps = None, None, 0
+            self.queue.appendleft(job)
+
+    def step(self, now: float, clock=None) -> list:
+        if self._admit(now):
+            self.changed = True
+        if self.changed:
+            self._rebuild()
+            self.changed = False
+        if self.running:
+            k = min(self.quantum, min(j.steps - j.done_steps for j in self.running))
+            if k > 0:
+                self.ex.advance(k)
+                self.steps_run += k
+                for j in self.running:
+                    j.done_steps += k
+        self.rounds += 1
+        finished = [j for j in self.running if j.done_steps >= j.steps]
+        t = clock() if clock else now
+        for j in finished:
+            j.result = self.ex.finish(j)
+            self.arena.free(j.offset)
+            j.finished = t
+            self.running.remove(j)
+            self.done.append(j)
+            self.changed = True
+        return finished
+
+
+def run_stream(server: Server, jobs, arrivals, clock=time.perf_counter, sleep=time.sleep):
+    """Feeds jobs to the server at their arrival times (seconds from the
+    start) and runs rounds until every job has finished.  Returns the
+    elapsed time."""
+    pending = collections.deque(sorted(zip(arrivals, range(len(jobs))), key=lambda p: p[0]))
+    t0 = clock()
+    now = lambda: clock() - t0  # noqa: E731
+    while pending or server.busy:
+        t = now()
+        while pending and pending[0][0] <= t:
+            at, k = pending.popleft()
+            server.submit(jobs[k], at)
+        if not server.busy:
+            sleep(max(0.0, pending[0][0] - t))
+            continue
+        server.step(t, now)
+    return now()
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> list:
+    """Arrival times (s) of a Poisson stream of the given rate (1/s)."""
+    rng = np.random.default_rng(seed)
+    return list(np.cumsum(rng.exponential(1.0 / rate, size=count)))
+
+
+def report(jobs, elapsed: float) -> dict:
+    lat = np.array([j.latency for j in jobs])
+    wait = np.array([j.admitted - j.arrival for j in jobs])
+    work = sum(j.nodes * j.steps for j in jobs)
+    return {
+        "jobs": len(jobs),
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+        "max_latency_s": round(float(lat.max()), 4),
+        "p50_queue_wait_s": round(float(np.percentile(wait, 50)), 4),
+        "elapsed_s": round(elapsed, 3),
+        "aggregate_mlups": round(work / elapsed / 1e6, 2),
+    }
+
+
+class ModelExecutor:
+    """Stand-in for the GPU: footprints and step times from a model, results
+    that record what was run.  Time advances on a virtual clock shared with
+    the caller (``now``), one quantum taking sum(nodes) / rate seconds per
+    step plus a fixed overhead."""
+
+    def __init__(self, rate: float = 1e10, overhead: float = 1e-4, bytes_per_node: int = 400):
+        self.rate, self.overhead, self.bpn = rate, overhead, bytes_per_node
+        self.t = 0.0
+        self.resident = {}
+        self.log = []
+
+    def now(self) -> float:
+        return self.t
+
+    def sleep(self, dt: float):
+        self.t += dt
+
+    def job_bytes(self, job) -> int:
+        return job.nodes * self.bpn + 4096
+
+    def start(self, job, offset) -> int:
+        self.resident[job.id] = {"offset": offset, "steps": 1, "nodes": job.nodes}
+        self.t += self.overhead
+        return 1
+
+    def table_bytes(self, running) -> dict:
+        out = {}
+        for j in running:
+            out[j.storage] = out.get(j.storage, 0) + j.nodes // 8 + 1024
+        return out
+
+    def rebuild(self, running, blocks):
+        self.log.append(("rebuild", sorted(j.id for j in running)))
+
+    def advance(self, n: int):
+        for r in self.resident.values():
+            r["steps"] += n
+        nodes = sum(r["nodes"] for r in self.resident.values())
+        self.log.append(("advance", n, sorted(self.resident)))
+        self.t += self.overhead + n * nodes / self.rate
+
+    def finish(self, job) -> dict:
+        r = self.resident.pop(job.id)
+        return {"steps": r["steps"], "offset": r["offset"]}
+
+    def drop(self, job):
+        self.resident.pop(job.id)
+
+
+class GpuExecutor:
+    """Device side of the server: one torch buffer as the arena, one
+    Simulation per resident job carved from it, one Batch per storage."""
+
+    def __init__(self, capacity: int, device="cuda:0"):
+        import torch
+
+        from . import dsm
+
+        self.dsm = dsm
+        dsm.load()  # raises if the HIP library is missing: there is no fallback
+        self.device = torch.device(device)
+        self.buffer = torch.empty(capacity + 2 * ALIGN, dtype=torch.uint8, device=self.device)
+        self.base = (self.buffer.data_ptr() + ALIGN - 1) // ALIGN * ALIGN
+        self.capacity = capacity
+        self.sims = {}
+        self.batches = {}
+        self.table_base = None
+
+    def set_table_base(self, base: int):
+        self.table_base = base
+
+    def _params(self, job):
+        w = job.workload
+        return self.dsm.make_params(w.dim, w.shape, w.kappa, w.alpha, w.tau, w.mobility, w.gravity,
+                                    storage=job.storage)
+
+    def job_bytes(self, job) -> int:
+        return self.dsm.dsm_required_bytes(self._params(job))
+
+    def start(self, job, offset) -> int:
+        from . import workloads as W
+
+        w = job.workload
+        f32 = lambda a: W.flat(np.asarray(a, dtype=np.float32).astype(np.float64))  # noqa: E731
+        sim = self.dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
+                                  gravity=w.gravity, storage=job.storage, device=self.device,
+                                  dev_ptr=self.base + offset)
+        sim.set_solid_field(f32(w.C1))
+        sim.set_liquid(f32(w.C2))
+        sim.step(1)  # the first step reads at-node populations; later steps run batched
+        self.sims[job.id] = sim
+        return 1
+
+    def table_bytes(self, running) -> dict:
+        groups = {}
+        for j in running:
+            groups.setdefault(j.storage, []).append(self.sims[j.id].handle)
+        return {k: self.dsm.dsm_batch_required_bytes(v) for k, v in groups.items()}
+
+    def rebuild(self, running, blocks):
+        for b in self.batches.values():
+            b.close()
+        self.batches = {}
+        groups = {}
+        for j in running:
+            groups.setdefault(j.storage, []).append(self.sims[j.id])
+        for key, sims in groups.items():
+            b = self.dsm.Batch(sims, device=self.device, dev_ptr=self.table_base + blocks[key])
+            b.tune()
+            self.batches[key] = b
+
+    def advance(self, n: int):
+        for b in self.batches.values():
+            b.step(n)
+
+    def finish(self, job) -> dict:
+        sim = self.sims.pop(job.id)
+        out = {"C2": sim.fields()["C2"], "mass": sim.mass(), "free_energy": sim.free_energy()[0],
+               "steps": sim.steps}
+        sim.close()
+        return out
+
+    def drop(self, job):
+        self.sims.pop(job.id).close()
+
+
+def make_gpu_server(capacity: int, quantum: int = 50, device="cuda:0") -> Server:
+    """A server whose arena and batch tables live in one device buffer of
+    ``capacity`` bytes."""
+    ex = GpuExecutor(capacity, device)
+    srv = Server(ex, capacity, quantum)
+    ex.set_table_base(ex.base + srv.arena.capacity)
+    return srv

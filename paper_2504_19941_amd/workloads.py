@@ -243,6 +243,80 @@ def batch_2d_sinusoid(count: int = 512, seed: int = 4, size_lo=(64, 32), size_hi
     return out
 
 
+def capillary_channel(width: int, length: int, theta_deg: float, gravity: float, wall: int = 4,
+                      alpha: float = 1.0, seed: int = 0) -> Workload:
+    """D3Q19 capillary filling: a square duct of ``width`` nodes (walls
+    ``wall`` thick on each side, so the periodic box is width + 2 wall
+    across) along x, fed from a liquid reservoir.  The duct axis is the
+    lattice's fastest axis, so a long duct fills whole wavefronts.  An end
+    plate fills x < wall; the reservoir x in [wall, xr) has no side walls,
+    the duct starts at xr = length / 4, and the liquid fills the reservoir up
+    to xr + 2.  Gravity -g along x.  C1 is the tanh profile of the signed
+    distance to the solid (union of duct walls and end plate, each a max/min
+    of plane distances)."""
+    n = width + 2 * wall
+    shape = (length, n, n)
+    X, Y, Z = _coords(shape)
+    c = 0.5 * (n - 1)
+    xr = length // 4
+    d_side = np.maximum(np.abs(Y - c), np.abs(Z - c)) - 0.5 * width        # > 0 inside the side walls
+    d_duct = np.minimum(d_side, X - (xr - 0.5))                              # walls only for x >= xr
+    d_plate = periodic_slab_distance(X, -0.5, wall - 0.5, length)
+    C1 = tanh_profile(np.maximum(d_duct, d_plate), alpha)
+    liquid = tanh_profile(np.minimum(X - (wall - 0.5), (xr + 2.0) - X), alpha)
+    C2 = liquid * (1.0 - C1)
+    return Workload(name=f"d3q19-channel-w{width}-L{length}-theta{theta_deg:.0f}", dim=3, shape=shape,
+                    kappa=kappas_for_angle(theta_deg), alpha=alpha, mask=(C1 > 0.5).astype(np.uint8),
+                    C1=C1, C2=C2, gravity=(-gravity, 0.0, 0.0), seed=seed)
+
+
+def particle_at_interface(n: int, radius: float, theta_deg: float, alpha: float = 1.0,
+                          seed: int = 0) -> Workload:
+    """D3Q19 n^3 periodic box with a diffuse spherical particle centred on
+    a flat liquid-gas interface: liquid fills n/8 <= z < n/2, the particle
+    centre sits on z = n/2 (the centre is offset by a seeded sub-node
+    shift)."""
+    rng = np.random.default_rng(seed)
+    shape = (n, n, n)
+    X, Y, Z = _coords(shape)
+    ctr = 0.5 * n + rng.uniform(-0.5, 0.5, size=3)
+    r = np.sqrt(sum(min_image(Xd - cd, n) ** 2 for Xd, cd in zip((X, Y, Z), ctr)))
+    C1 = tanh_profile(radius - r, alpha)
+    C2 = tanh_profile(periodic_slab_distance(Z, n / 8.0, ctr[2], n), alpha) * (1.0 - C1)
+    return Workload(name=f"d3q19-particle-{n}^3-R{radius:.1f}-theta{theta_deg:.0f}", dim=3, shape=shape,
+                    kappa=kappas_for_angle(theta_deg), alpha=alpha, mask=(C1 > 0.5).astype(np.uint8),
+                    C1=C1, C2=C2, seed=seed)
+
+
+SERVE_RECIPE = ("Poisson arrivals; half capillary-filling jobs (square duct width 8-32, length 128-512, "
+                "gravity 1e-6-1e-5, theta 30-80 deg), half particle-at-interface jobs (n^3 box n 96-160, "
+                "particle radius 10-20, theta 45-135 deg)")
+
+
+def serve_jobs(count: int, seed: int = 5, steps=(200, 1000), small: bool = False) -> list:
+    """The job mix of the served form, drawn from one seed: (workload, steps)
+    pairs, alternating at random between the two kinds.  ``small`` shrinks
+    every lattice (for tests) while keeping both kinds."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        if rng.uniform() < 0.5:
+            width = int(rng.integers(8, 33))
+            length = int(rng.integers(128, 513))
+            if small:
+                width, length = max(6, width // 4), max(24, length // 8)
+            g = float(10.0 ** rng.uniform(-6.0, -5.0))
+            w = capillary_channel(width, length, float(rng.uniform(30.0, 80.0)), g, seed=seed * 7919 + k)
+        else:
+            n = int(rng.integers(96, 161))
+            radius = float(rng.uniform(10.0, 20.0))
+            if small:
+                n, radius = max(24, n // 4), max(4.0, radius / 4)
+            w = particle_at_interface(n, radius, float(rng.uniform(45.0, 135.0)), seed=seed * 7919 + k)
+        out.append((w, int(rng.integers(steps[0], steps[1] + 1))))
+    return out
+
+
 def random_postcollision_state(Q: int, shape, C2: np.ndarray, seed: int, amp: float = 1e-3):
     """Seeded random post-collision populations around a liquid field:
     f* = amp * U(-1, 1); g*_0 = C2 + amp * U(-1, 1); g*_i = amp * U(-1, 1)

@@ -1,0 +1,86 @@
+"""Served form on the GPU: jobs of both kinds (capillary ducts, particles at
+an interface; FP32 and FP16 storage) submitted while others run, admitted by
+footprint into one device arena, advanced together by the batched step, give
+exactly the result each gives alone."""
+import numpy as np
+import pytest
+
+from paper_2504_19941_amd import dsm
+from paper_2504_19941_amd import serve as S
+from paper_2504_19941_amd import workloads as W
+
+from .conftest import f32
+
+pytestmark = pytest.mark.gpu
+
+
+def alone(job):
+    w = job.workload
+    sim = dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
+                         gravity=w.gravity, storage=job.storage)
+    sim.set_solid_field(f32(W.flat(w.C1)))
+    sim.set_liquid(f32(W.flat(w.C2)))
+    sim.step(job.steps)
+    out = {"C2": sim.fields()["C2"], "mass": sim.mass(), "steps": sim.steps}
+    sim.close()
+    return out
+
+
+def make_jobs(count, seed):
+    pairs = W.serve_jobs(count, seed=seed, steps=(15, 70), small=True)
+    return [S.Job(k, w, n, storage=dsm.DSM_STORAGE_FP16 if k % 3 == 2 else dsm.DSM_STORAGE_FP32)
+            for k, (w, n) in enumerate(pairs)]
+
+
+def check_alone(jobs):
+    for j in jobs:
+        ref = alone(j)
+        assert j.result["steps"] == j.steps == ref["steps"]
+        same = np.array_equal(j.result["C2"], ref["C2"])
+        err = float(np.abs(j.result["C2"] - ref["C2"]).max())
+        print(f"  job {j.id} {j.workload.name} steps {j.steps} storage {j.storage}: max |dC2| {err:.1e}",
+              flush=True)
+        assert same, f"job {j.id} differs from its run alone"
+        assert np.array_equal(j.result["mass"], ref["mass"])
+
+
+def test_jobs_joining_mid_run_match_their_runs_alone(gpu):
+    jobs = make_jobs(6, seed=21)
+    srv = S.make_gpu_server(256 << 20, quantum=7)
+    srv.submit(jobs[0], 0.0)
+    srv.step(0.0)
+    srv.submit(jobs[1], 0.1)
+    srv.step(0.1)
+    srv.step(0.2)
+    for j in jobs[2:]:
+        srv.submit(j, 0.3)
+    rounds = 0
+    while srv.busy:
+        srv.step(1.0)
+        rounds += 1
+        assert rounds < 1000
+    assert len(srv.done) == len(jobs)
+    check_alone(jobs)
+
+
+def test_admission_by_footprint_queues_and_completes(gpu):
+    """An arena that holds about two of the jobs at once: the rest wait in
+    order, and every job still ends exactly as alone."""
+    jobs = make_jobs(5, seed=33)
+    probe = S.GpuExecutor(1 << 20)
+    sizes = [probe.job_bytes(j) for j in jobs]
+    del probe
+    cap = (16 << 20) + 2 * max(sizes) + (1 << 20)
+    srv = S.make_gpu_server(cap, quantum=9)
+    for j in jobs:
+        srv.submit(j, 0.0)
+    peak_jobs = 0
+    while srv.busy:
+        srv.step(float(srv.rounds))  # the round number serves as the clock
+        peak_jobs = max(peak_jobs, len(srv.running))
+        assert srv.arena.used <= srv.arena.capacity
+    print(f"  footprints {sizes}, arena {srv.arena.capacity}, at most {peak_jobs} resident", flush=True)
+    assert 1 <= peak_jobs < len(jobs)
+    adm = [j.admitted for j in jobs]
+    assert adm == sorted(adm)
+    check_alone(jobs)
