@@ -55,6 +55,7 @@ struct dsmo_sim {
     double *fs, *gs;     /* post-collision populations, [Q][N] */
     double *phi, *mu, *p_t;
     double *F, *u;       /* [3][N] */
+    double *rho, *grho;  /* local density [N] and its gradient [3][N] */
     long* nb;            /* nb[i*N + n] = index of n + c_i (periodic) */
     int stage;           /* 0 nothing live, 1 solid stage live, 2 fluid stage live */
     /* solid-stage settings of the live solid-stage state */
@@ -173,8 +174,8 @@ void dsmo_equilibrium_g(int dim, double C, double mu, const double u[3], double*
 
 /* Forcing term (Sec. II.B):
  *   F_i = (1 - 1/(2 tau)) w_i [ ((c_i - u) . grad rho) s_i(u) + c_i . F / c_s^2 ]
- * with tau the local hydrodynamic relaxation time.  The hot path has
- * rho_2 = rho_3, so grad rho = 0 there. */
+ * with tau the local hydrodynamic relaxation time (the density enters
+ * only through grad rho). */
 void dsmo_forcing(int dim, double tau, double rho, const double u[3],
                   const double grad_rho[3], const double F[3], double* Fi) {
     (void)rho;
@@ -203,6 +204,7 @@ int dsmo_create(const dsmo_params* p, const unsigned char* mask, dsmo_sim** out)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return DSMO_EINVAL;
     if (p->dim == 2 && p->nz != 1) return DSMO_EINVAL;
     if (!(p->tau > 0.5) || !(p->mobility > 0.0) || !(p->alpha > 0.0)) return DSMO_EINVAL;
+    if (!(p->rho_liquid > 0.0) || !(p->rho_gas > 0.0) || !(p->tau_gas > 0.5)) return DSMO_EINVAL;
     for (int k = 0; k < 3; ++k)
         if (!(p->kappa[k] >= 0.0)) return DSMO_EINVAL;
 
@@ -227,6 +229,8 @@ int dsmo_create(const dsmo_params* p, const unsigned char* mask, dsmo_sim** out)
     s->p_t = (double*)zalloc(N * sizeof(double));
     s->F = (double*)zalloc(3 * N * sizeof(double));
     s->u = (double*)zalloc(3 * N * sizeof(double));
+    s->rho = (double*)zalloc(N * sizeof(double));
+    s->grho = (double*)zalloc(3 * N * sizeof(double));
     s->nb = (long*)zalloc(Q * N * sizeof(long));
     if (!s->nb) {
         dsmo_destroy(s);
@@ -236,7 +240,7 @@ int dsmo_create(const dsmo_params* p, const unsigned char* mask, dsmo_sim** out)
         for (size_t n = 0; n < N; ++n)
             s->nb[i * N + n] = shift(s, (long)n, s->c[i][0], s->c[i][1], s->c[i][2]);
     if (!s->mask || !s->C1 || !s->f || !s->g || !s->fs || !s->gs || !s->phi || !s->mu ||
-        !s->p_t || !s->F || !s->u) {
+        !s->p_t || !s->F || !s->u || !s->rho || !s->grho) {
         dsmo_destroy(s);
         return DSMO_ENOMEM;
     }
@@ -261,6 +265,8 @@ void dsmo_destroy(dsmo_sim* s) {
     free(s->p_t);
     free(s->F);
     free(s->u);
+    free(s->rho);
+    free(s->grho);
     free(s->nb);
     free(s);
 }
@@ -368,7 +374,39 @@ static void stage_force(dsmo_sim* s) {
     }
 }
 
-/* Hydrodynamic moments (Sec. II.B), rho = 1 and grad rho = 0:
+/* Local density of the fluid stage (Sec. II.B):
+ *   rho = rho_3 + (rho_2 - rho_3) C2 / (C2 + C3),
+ * where C2 + C3 = 1 - C1.  Inside the solid both fluid concentrations
+ * vanish, so the fraction is read with its denominator floored at 1e-6 and
+ * the fraction clamped to [0, 1] (the paper does not say what the ratio is
+ * where no fluid is present).  grad rho by the isotropic central difference
+ * used for every other gradient.  The solid stage has rho = 1. */
+static double density_at(const dsmo_sim* s, long n) {
+    if (s->stage != 2) return 1.0;
+    double C2 = s->phi[n], C3 = 1.0 - s->C1[n] - C2;
+    double den = C2 + C3;
+    if (den < 1e-6) den = 1e-6;
+    double frac = C2 / den;
+    if (frac < 0.0) frac = 0.0;
+    if (frac > 1.0) frac = 1.0;
+    return s->p.rho_gas + (s->p.rho_liquid - s->p.rho_gas) * frac;
+}
+
+static void stage_density(dsmo_sim* s) {
+    long N = s->N;
+#pragma omp parallel for num_threads(threads_of(s)) schedule(static)
+    for (long n = 0; n < N; ++n) s->rho[n] = density_at(s, n);
+#pragma omp parallel for num_threads(threads_of(s)) schedule(static)
+    for (long n = 0; n < N; ++n) {
+        double gr[3];
+        grad(s, s->rho, n, gr);
+        s->grho[0 * N + n] = gr[0];
+        s->grho[1 * N + n] = gr[1];
+        s->grho[2 * N + n] = gr[2];
+    }
+}
+
+/* Hydrodynamic moments (Sec. II.B):
  *   rho u = sum_i c_i f_i + F/2,   p~ = sum_i f_i + u . grad rho / 2.
  * The half-force correction uses the same total force F that enters the
  * forcing term, mu grad phi plus the body force (the typeset correction
@@ -390,15 +428,25 @@ static void stage_velocity(dsmo_sim* s) {
             my += s->c[i][1] * fi;
             mz += s->c[i][2] * fi;
         }
-        const double rho = 1.0;
-        s->u[0 * N + n] = (mx + 0.5 * s->F[0 * N + n]) / rho;
-        s->u[1 * N + n] = (my + 0.5 * s->F[1 * N + n]) / rho;
-        s->u[2 * N + n] = (mz + 0.5 * s->F[2 * N + n]) / rho;
-        s->p_t[n] = m0; /* + u . grad rho / 2, zero here */
+        const double rho = s->rho[n];
+        double ux = (mx + 0.5 * s->F[0 * N + n]) / rho;
+        double uy = (my + 0.5 * s->F[1 * N + n]) / rho;
+        double uz = (mz + 0.5 * s->F[2 * N + n]) / rho;
+        s->u[0 * N + n] = ux;
+        s->u[1 * N + n] = uy;
+        s->u[2 * N + n] = uz;
+        s->p_t[n] = m0 + 0.5 * (ux * s->grho[0 * N + n] + uy * s->grho[1 * N + n] + uz * s->grho[2 * N + n]);
     }
 }
 
-static double relax_tau(const dsmo_sim* s) { return s->stage == 1 ? s->tau_s : s->p.tau; }
+/* Local relaxation time: tau_s in the solid stage; in the fluid stage
+ * tau = tau_3 + (tau_2 - tau_3) H(C2 - C3) (Sec. II.B), with the step
+ * H(x) = 1 for x > 0 and 0 otherwise. */
+static double relax_tau(const dsmo_sim* s, long n) {
+    if (s->stage == 1) return s->tau_s;
+    double C2 = s->phi[n], C3 = 1.0 - s->C1[n] - C2;
+    return C2 - C3 > 0.0 ? s->p.tau : s->p.tau_gas;
+}
 static double relax_tau_g(const dsmo_sim* s) {
     return s->stage == 1 ? s->tau_gs : 0.5 + s->p.mobility / CS2;
 }
@@ -408,7 +456,7 @@ static double relax_tau_g(const dsmo_sim* s) {
 static void stage_collide(dsmo_sim* s) {
     long N = s->N;
     int Q = s->Q, dim = s->p.dim;
-    double tau = relax_tau(s), tau_g = relax_tau_g(s);
+    double tau_g = relax_tau_g(s);
 #pragma omp parallel for num_threads(threads_of(s)) schedule(static)
     for (long n = 0; n < N; ++n) {
         double u[3] = {s->u[0 * N + n], s->u[1 * N + n], s->u[2 * N + n]};
@@ -416,10 +464,11 @@ static void stage_collide(dsmo_sim* s) {
         if (is_solid(s, n)) {
             for (int i = 0; i < Q; ++i) s->fs[(size_t)i * N + n] = 0.0;
         } else {
-            const double zero[3] = {0.0, 0.0, 0.0};
+            double tau = relax_tau(s, n);
+            double gr[3] = {s->grho[0 * N + n], s->grho[1 * N + n], s->grho[2 * N + n]};
             double F[3] = {s->F[0 * N + n], s->F[1 * N + n], s->F[2 * N + n]};
-            dsmo_equilibrium_f(dim, s->p_t[n], 1.0, u, feq);
-            dsmo_forcing(dim, tau, 1.0, u, zero, F, Fi);
+            dsmo_equilibrium_f(dim, s->p_t[n], s->rho[n], u, feq);
+            dsmo_forcing(dim, tau, s->rho[n], u, gr, F, Fi);
             for (int i = 0; i < Q; ++i) {
                 double fi = s->f[(size_t)i * N + n];
                 s->fs[(size_t)i * N + n] = fi - (fi - feq[i]) / tau + Fi[i];
@@ -512,6 +561,7 @@ static void observe(dsmo_sim* s) {
     stage_moment(s);
     stage_chemical_potential(s);
     stage_force(s);
+    stage_density(s);
     stage_velocity(s);
 }
 
@@ -640,7 +690,7 @@ int dsmo_free_energy(dsmo_sim* s, double* Fout, double* Ekin) {
         }
         if (!is_solid(s, n)) {
             double ux = s->u[n], uy = s->u[N + n], uz = s->u[2 * N + n];
-            E += 0.5 * (ux * ux + uy * uy + uz * uz);
+            E += 0.5 * s->rho[n] * (ux * ux + uy * uy + uz * uz);
         }
     }
     if (Fout) *Fout = F;

@@ -53,6 +53,13 @@ typedef struct {
     double gravity[3];   /* body-force density acting on the liquid: F_g = C2 g */
     int confine_reading; /* DSMO_CONFINE_* */
     int threads;         /* OpenMP threads for node loops (<= 1: serial) */
+    /* Density and viscosity contrast of the fluid stage (Sec. II.B):
+     * rho = rho_3 + (rho_2 - rho_3) C2 / (C2 + C3) and
+     * tau = tau_3 + (tau_2 - tau_3) H(C2 - C3), with tau_2 = tau above.
+     * rho_liquid = rho_gas = 1 and tau_gas = tau give the uniform fluid. */
+    double rho_liquid;   /* rho_2 > 0 */
+    double rho_gas;      /* rho_3 > 0 */
+    double tau_gas;      /* tau_3 > 1/2 */
 } dsmo_params;
 
 typedef struct dsmo_sim dsmo_sim;

@@ -15,7 +15,9 @@ Readings are the same as the C oracle's (stated there): the surface-tension
 force in the potential form mu grad C, the half-force velocity correction
 with the total force, the rest population of g_eq closing the zeroth moment,
 s_i with -u.u / (2 c_s^2), the confining potential acting on solid outside
-and fluid inside S, and the Omega terms acting outside [0, 1].
+and fluid inside S, the Omega terms acting outside [0, 1], and for the
+density and viscosity contrast the floored fraction C2 / (C2 + C3) and the
+step H(x) = 1 for x > 0.
 """
 from __future__ import annotations
 
@@ -51,8 +53,10 @@ def lattice(dim):
 
 class MiniOracle:
     def __init__(self, dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
-                 mask=None, bounce="interpolated"):
+                 mask=None, bounce="interpolated", rho=(1.0, 1.0), tau_gas=None):
         self.dim, self.shape = dim, tuple(shape)
+        self.rho2, self.rho3 = rho
+        self.tau3 = tau if tau_gas is None else tau_gas
         self.c, self.w = lattice(dim)
         self.Q = len(self.w)
         self.k1, self.k2, self.k3 = kappa
@@ -152,21 +156,41 @@ class MiniOracle:
         if self.stage == 2:
             F = F + phi * self.grav.reshape((self.dim,) + (1,) * self.dim)
         F[:, solid] = 0.0
+        rho = self._density(phi)
+        grho = self.grad(rho)
         mom = np.tensordot(self.c.T.astype(float), self.f, axes=1)
-        u = mom + 0.5 * F
+        u = (mom + 0.5 * F) / rho
         u[:, solid] = 0.0
-        p = self.f.sum(axis=0)
+        p = self.f.sum(axis=0) + 0.5 * (u * grho).sum(axis=0)
         p[solid] = 0.0
+        self._rho, self._grho = rho, grho
         return phi, mu, F, u, p, solid
+
+    def _density(self, phi):
+        """rho_3 + (rho_2 - rho_3) C2 / (C2 + C3), the fraction's denominator
+        1 - C1 floored at 1e-6 and the fraction clipped to [0, 1]; 1 in the
+        solid stage."""
+        if self.stage != 2:
+            return np.ones(self.shape)
+        frac = np.clip(phi / np.maximum(1.0 - self.C1, 1e-6), 0.0, 1.0)
+        return self.rho3 + (self.rho2 - self.rho3) * frac
 
     def _step(self):
         phi, mu, F, u, p, solid = self.observe()
-        tau = self._tau_s if self.stage == 1 else self.tau
+        rho, grho = self._rho, self._grho
+        if self.stage == 1:
+            tau = np.full(self.shape, self._tau_s)
+        else:
+            C3 = 1.0 - self.C1 - phi
+            tau = np.where(phi - C3 > 0.0, self.tau, self.tau3)
         tau_g = self._tau_gs if self.stage == 1 else self.tau_g
         fs = np.empty_like(self.f)
         for i in range(self.Q):
-            feq = self.w[i] * (p + self._s(i, u))
-            Fi = (1 - 0.5 / tau) * self.w[i] * np.tensordot(self.c[i].astype(float), F, axes=1) / CS2
+            ci = self.c[i].astype(float)
+            s = self._s(i, u)
+            feq = self.w[i] * (p + rho * s)
+            cu_grad = np.tensordot(ci, grho, axes=1) - (u * grho).sum(axis=0)
+            Fi = (1 - 0.5 / tau) * self.w[i] * (cu_grad * s + np.tensordot(ci, F, axes=1) / CS2)
             fs[i] = self.f[i] - (self.f[i] - feq) / tau + Fi
         fs[:, solid] = 0.0
         geq = self._geq(phi, mu, u)

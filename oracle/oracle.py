@@ -25,6 +25,7 @@ class _Params(ctypes.Structure):
         ("kappa", ctypes.c_double * 3), ("alpha", ctypes.c_double), ("tau", ctypes.c_double),
         ("mobility", ctypes.c_double), ("gravity", ctypes.c_double * 3),
         ("confine_reading", ctypes.c_int), ("threads", ctypes.c_int),
+        ("rho_liquid", ctypes.c_double), ("rho_gas", ctypes.c_double), ("tau_gas", ctypes.c_double),
     ]
 
 
@@ -116,7 +117,9 @@ class Oracle:
 
     def __init__(self, dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1,
                  gravity=(0.0, 0.0, 0.0), mask=None, threads=1,
-                 confine_reading=CONFINE_PURPOSE):
+                 confine_reading=CONFINE_PURPOSE, rho=(1.0, 1.0), tau_gas=None):
+        """rho = (rho_2, rho_3) of liquid and gas; tau_gas = tau_3 (default:
+        tau, i.e. no viscosity contrast)."""
         lib = load()
         nx, ny = shape[0], shape[1]
         nz = shape[2] if dim == 3 else 1
@@ -128,6 +131,8 @@ class Oracle:
         p.alpha, p.tau, p.mobility = float(alpha), float(tau), float(mobility)
         p.gravity[:] = [float(g) for g in gravity]
         p.confine_reading, p.threads = int(confine_reading), int(threads)
+        p.rho_liquid, p.rho_gas = float(rho[0]), float(rho[1])
+        p.tau_gas = float(tau if tau_gas is None else tau_gas)
         h = ctypes.c_void_p()
         m = None
         if mask is not None:

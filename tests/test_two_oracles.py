@@ -1,6 +1,6 @@
 """The C oracle and the independent NumPy oracle agree to round-off on small
 lattices, in both stages, with walls, a curved particle, interpolated
-bounce-back and a body force."""
+bounce-back, a body force, and density and viscosity contrast."""
 import numpy as np
 import pytest
 
@@ -71,6 +71,30 @@ def test_random_postcollision_state(oracle_lib, dim, shape):
     m.set_postcollision(fs, gs)
     o.step(3)
     m.step(3)
+    po, pm = o.get_populations(), m.populations()
+    assert np.abs(po[0] - pm[0]).max() < 1e-13
+    assert np.abs(po[1] - pm[1]).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim,shape", CASES)
+def test_fluid_stage_with_density_and_viscosity_contrast(oracle_lib, dim, shape):
+    mask, C1, C2 = wall_and_particle(dim, shape, thickness=2, radius=2.5, seed=5)
+    k = W.kappas_for_angle(60.0)
+    grav = (2e-4, -1e-4, 1e-4)[:dim] + (0.0,) * (3 - dim)
+    kw = dict(gravity=grav, rho=(1.0, 0.4), tau_gas=0.62)
+    o = Oracle(dim, shape, k, mask=W.flat(mask), **kw)
+    m = MiniOracle(dim, shape, k, mask=mask, **kw)
+    o.set_solid_field(W.flat(C1))
+    m.set_solid_field(C1)
+    o.set_liquid(W.flat(C2))
+    m.set_liquid(C2)
+    o.step(100)
+    m.step(100)
+    fo, fm = o.fields(), m.fields()
+    for key in ("C2", "p"):
+        assert np.abs(fo[key] - fm[key]).max() < 1e-13
+    assert np.abs(fo["u"] - fm["u"]).max() < 1e-13
+    assert np.abs(fo["u"]).max() > 1e-6  # the flow is not trivial
     po, pm = o.get_populations(), m.populations()
     assert np.abs(po[0] - pm[0]).max() < 1e-13
     assert np.abs(po[1] - pm[1]).max() < 1e-13
