@@ -82,14 +82,19 @@ typedef struct {
                             kappa_2 + kappa_3 > 0); Sec. II.A bulk and gradient
                             energies with kappa'_n = alpha^2 kappa_n              */
     double alpha;        /* interface width (> 0); the paper uses 1               */
-    double tau;          /* hydrodynamic relaxation time (> 1/2); rho = 1 and a
-                            single tau for both fluids                          */
+    double tau;          /* hydrodynamic relaxation time tau_2 of the liquid
+                            (> 1/2); the gas takes tau_gas                       */
     double mobility;     /* Cahn-Hilliard mobility M (> 0): tau_g = 1/2 + 3 M    */
     double gravity[3];   /* body-force density on the liquid, F_g = C2 g          */
     int reduce_every;    /* K > 0: dsm_step checks for non-finite values every
                             K steps (synchronising); 0 disables the check        */
     int kernel;          /* DSM_KERNEL_FUSED (default) or DSM_KERNEL_SPLIT        */
     int storage;         /* DSM_STORAGE_FP32 (default) or DSM_STORAGE_FP16        */
+    double rho[2];       /* densities rho_2 (liquid), rho_3 (gas) of Sec. II.B:
+                            rho = rho_3 + (rho_2 - rho_3) C2 / (C2 + C3); each
+                            > 0, or 0 for 1                                       */
+    double tau_gas;      /* tau_3 of Sec. II.B: tau = tau_3 + (tau - tau_3)
+                            H(C2 - C3); > 1/2, or 0 for tau (no contrast)         */
 } dsm_params;
 
 typedef struct dsm_sim dsm_sim;
@@ -239,7 +244,7 @@ typedef struct dsm_batch_schedule {
 size_t dsm_batch_required_bytes(dsm_sim* const* sims, int count);
 
 /* Builds the batch and its tables on `stream` (synchronises it).  Default
- * schedules: 3D variant 2 with 16 planes, 2D variant 2 with 32 planes, all
+ * schedules: 3D variant 2 with 16 planes, 2D variant 0 with 32 planes, all
  * resident workgroups. */
 int dsm_batch_create(dsm_sim* const* sims, int count, void* dev_buf, size_t dev_bytes, void* stream,
                      dsm_batch** out);

@@ -66,6 +66,10 @@ const char* validate(const dsm_params* p) {
     if (p->reduce_every < 0) return "reduce_every must be >= 0";
     if (p->kernel != DSM_KERNEL_FUSED && p->kernel != DSM_KERNEL_SPLIT) return "unknown kernel";
     if (p->storage != DSM_STORAGE_FP32 && p->storage != DSM_STORAGE_FP16) return "unknown storage";
+    for (int k = 0; k < 2; ++k)
+        if (!(p->rho[k] >= 0.0) || !isfinite(p->rho[k])) return "rho must be finite and > 0 (0 selects 1)";
+    if (!(p->tau_gas == 0.0 || p->tau_gas > 0.5) || !isfinite(p->tau_gas))
+        return "tau_gas must be > 1/2 (0 selects tau)";
     return nullptr;
 }
 
@@ -140,6 +144,14 @@ Phys dsm::sim_phys(const dsm_sim* s, int stage) {
     ph.beta = (float)s->beta;
     ph.omega = (float)s->omega;
     ph.stage = stage;
+    // density and viscosity contrast (fluid stage only)
+    const double r2 = s->p.rho[0] > 0.0 ? s->p.rho[0] : 1.0, r3 = s->p.rho[1] > 0.0 ? s->p.rho[1] : 1.0;
+    const double tau3 = s->p.tau_gas > 0.0 ? s->p.tau_gas : s->p.tau;
+    ph.rho2 = (float)r2;
+    ph.rho3 = (float)r3;
+    ph.inv_tau3 = (float)(1.0 / tau3);
+    ph.fpref_gas = (float)(1.0 - 0.5 / tau3);
+    ph.contrast = stage == 2 && (r2 != 1.0 || r3 != 1.0 || tau3 != s->p.tau) ? 1 : 0;
     return ph;
 }
 

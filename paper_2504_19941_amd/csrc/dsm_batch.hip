@@ -26,7 +26,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxPlanes = 4096;
-constexpr int kNumCounters = 2;
+constexpr int kGroups = 4;        // (2D, 3D) x (uniform fluid, density/viscosity contrast)
+constexpr int kNumCounters = kGroups;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -38,6 +39,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
     } while (0)
 
 int type_index(int dim) { return dim == 2 ? 0 : 1; }
+int contrast_of(const dsm_sim* s) { return sim_phys(s, 2).contrast; }
+// Work group of a member: lattice type and contrast variant of the kernel.
+int group_of(const dsm_sim* s) { return 2 * type_index(s->p.dim) + contrast_of(s); }
+int group_dim(int t) { return t < 2 ? 2 : 3; }
 
 // Smallest tile of each lattice type (bounds the work list for any schedule).
 void min_tile(int dim, int* tx, int* ty) {
@@ -53,7 +58,7 @@ void min_tile(int dim, int* tx, int* ty) {
 }
 
 struct Caps {
-    size_t items[2];
+    size_t items[kGroups];
     size_t chunks;
 };
 
@@ -72,13 +77,13 @@ const char* check_members(dsm_sim* const* sims, int count) {
 }
 
 Caps member_caps(dsm_sim* const* sims, int count) {
-    Caps c{{0, 0}, 0};
+    Caps c{{0, 0, 0, 0}, 0};
     for (int k = 0; k < count; ++k) {
         const dsm_sim* s = sims[k];
         int tx = 0, ty = 0;
         min_tile(s->p.dim, &tx, &ty);
         const Geom& g = s->geom;
-        c.items[type_index(s->p.dim)] +=
+        c.items[group_of(s)] +=
             (size_t)((g.X + tx - 1) / tx) * (size_t)((g.Y + ty - 1) / ty) * (size_t)g.Z;
         c.chunks += (size_t)((kLinksPerNode * s->N + kBatchChunk - 1) / kBatchChunk);
     }
@@ -86,7 +91,7 @@ Caps member_caps(dsm_sim* const* sims, int count) {
 }
 
 struct Offsets {
-    size_t inst, items[2], chunks, counters, flags, total;
+    size_t inst, items[kGroups], chunks, counters, flags, total;
 };
 
 Offsets make_offsets(int count, const Caps& c) {
@@ -98,8 +103,7 @@ Offsets make_offsets(int count, const Caps& c) {
         return r;
     };
     o.inst = take((size_t)count * sizeof(BatchInst));
-    o.items[0] = take(c.items[0] * sizeof(BatchItem));
-    o.items[1] = take(c.items[1] * sizeof(BatchItem));
+    for (int k = 0; k < kGroups; ++k) o.items[k] = take(c.items[k] * sizeof(BatchItem));
     o.chunks = take(c.chunks * sizeof(BatchChunk));
     o.counters = take(kNumCounters * sizeof(int));
     o.flags = take((size_t)count * sizeof(int));
@@ -117,13 +121,13 @@ struct dsm_batch {
     int cus = 1;
     Caps caps{};
     BatchInst* inst_dev = nullptr;
-    BatchItem* items_dev[2] = {nullptr, nullptr};
+    BatchItem* items_dev[kGroups] = {nullptr, nullptr, nullptr, nullptr};
     BatchChunk* chunks_dev = nullptr;
     int* counters = nullptr;
     int* flags_dev = nullptr;
-    bool present[2] = {false, false};
-    dsm_batch_schedule sched[2]{};
-    int nitems[2] = {0, 0};
+    bool present[kGroups] = {false, false, false, false};
+    dsm_batch_schedule sched[2]{};  // by lattice type (2D, 3D)
+    int nitems[kGroups] = {0, 0, 0, 0};
     int nchunks = 0;
     std::vector<BatchInst> inst_host, inst_sent;
     std::vector<BatchChunk> chunks_host, chunks_sent;
@@ -143,24 +147,24 @@ void drop_graphs(dsm_batch* b) {
 }
 
 int grid_of(const dsm_batch* b, int t) {
-    const int dim = t == 0 ? 2 : 3;
-    const dsm_batch_schedule& s = b->sched[t];
-    const int per_cu = s.blocks_per_cu > 0 ? s.blocks_per_cu : batch_blocks_per_cu(dim, s.variant, b->half);
+    const dsm_batch_schedule& s = b->sched[t >> 1];
+    const int per_cu =
+        s.blocks_per_cu > 0 ? s.blocks_per_cu : batch_blocks_per_cu(group_dim(t), s.variant, b->half, t & 1);
     return std::max(1, per_cu) * b->cus;
 }
 
-// Work list of lattice type t for its schedule: every tile of every member
-// of that type, costliest (most planes) first, members in order otherwise.
+// Work list of group t for its schedule: every tile of every member of the
+// group, costliest (most planes) first, members in order otherwise.
 int build_items(dsm_batch* b, int t) {
-    const int dim = t == 0 ? 2 : 3;
-    const dsm_batch_schedule& s = b->sched[t];
+    const int dim = group_dim(t);
+    const dsm_batch_schedule& s = b->sched[t >> 1];
     int tx = 0, ty = 0;
     fused_tile_shape(dim, s.variant, &tx, &ty);
     auto& it = b->items_host;
     it.clear();
     for (int k = 0; k < (int)b->sims.size(); ++k) {
         const dsm_sim* m = b->sims[k];
-        if (m->p.dim != dim) continue;
+        if (group_of(m) != t) continue;
         const Geom& g = m->geom;
         for (int z0 = 0; z0 < g.Z; z0 += s.planes)
             for (int y0 = 0; y0 < g.Y; y0 += ty)
@@ -239,10 +243,11 @@ int refresh(dsm_batch* b) {
 // Launches of one step with the given parity on stream st.
 hipError_t enqueue_step(dsm_batch* b, int parity, hipStream_t st) {
     hipError_t e = launch_bounce_batch(b->inst_dev, b->chunks_dev, b->nchunks, parity, b->counters, kNumCounters, st);
-    for (int t = 0; t < 2 && e == hipSuccess; ++t)
+    for (int t = 0; t < kGroups && e == hipSuccess; ++t)
         if (b->present[t])
-            e = launch_step_batch(t == 0 ? 2 : 3, b->sched[t].variant, b->half, b->inst_dev, b->items_dev[t],
-                                  b->nitems[t], b->counters + t, grid_of(b, t), parity, b->sched[t].planes, st);
+            e = launch_step_batch(group_dim(t), b->sched[t >> 1].variant, b->half, t & 1, b->inst_dev,
+                                  b->items_dev[t], b->nitems[t], b->counters + t, grid_of(b, t), parity,
+                                  b->sched[t >> 1].planes, st);
     return e;
 }
 
@@ -315,21 +320,27 @@ constexpr double kWaveCost[2][3] = {{1.0, 1.35, 1.58}, {1.08, 1.06, 1.0}};
 // first, keeps every resident wave busy until the list is drained, so the
 // step lasts the total work over the resident waves plus a tail charged at
 // a quarter of the longest item.
-double schedule_cost(const dsm_batch* b, int dim, int variant, int planes, int per_cu) {
+double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
     int tx = 0, ty = 0;
     fused_tile_shape(dim, variant, &tx, &ty);
     const double waves_per_item = (double)(tx / 64) * ty;
-    double total = 0.0, longest = 0.0;
-    for (const dsm_sim* m : b->sims) {
-        if (m->p.dim != dim) continue;
-        const Geom& g = m->geom;
-        const double tiles = (double)((g.X + tx - 1) / tx) * (double)((g.Y + ty - 1) / ty);
-        const int full = g.Z / planes, tail = g.Z % planes;
-        total += tiles * waves_per_item * ((double)full * (planes + 2) + (tail ? tail + 2 : 0));
-        longest = std::max(longest, (double)(full ? planes + 2 : tail + 2));
+    double cost = 0.0;
+    for (int t = 2 * type_index(dim); t < 2 * type_index(dim) + 2; ++t) {
+        if (!b->present[t]) continue;
+        double total = 0.0, longest = 0.0;
+        for (const dsm_sim* m : b->sims) {
+            if (group_of(m) != t) continue;
+            const Geom& g = m->geom;
+            const double tiles = (double)((g.X + tx - 1) / tx) * (double)((g.Y + ty - 1) / ty);
+            const int full = g.Z / planes, tail = g.Z % planes;
+            total += tiles * waves_per_item * ((double)full * (planes + 2) + (tail ? tail + 2 : 0));
+            longest = std::max(longest, (double)(full ? planes + 2 : tail + 2));
+        }
+        const int per_cu = batch_blocks_per_cu(dim, variant, b->half, t & 1);
+        const double resident_waves = (double)b->cus * per_cu * waves_per_item;
+        cost += kWaveCost[dim - 2][variant] * (total / resident_waves + 0.25 * longest);
     }
-    const double resident_waves = (double)b->cus * per_cu * waves_per_item;
-    return kWaveCost[dim - 2][variant] * (total / resident_waves + 0.25 * longest);
+    return cost;
 }
 
 }  // namespace
@@ -366,13 +377,12 @@ int dsm_batch_create(dsm_sim* const* sims, int count, void* dev_buf, size_t dev_
     b->caps = caps;
     char* base = (char*)dev_buf;
     b->inst_dev = (BatchInst*)(base + o.inst);
-    b->items_dev[0] = (BatchItem*)(base + o.items[0]);
-    b->items_dev[1] = (BatchItem*)(base + o.items[1]);
+    for (int k = 0; k < kGroups; ++k) b->items_dev[k] = (BatchItem*)(base + o.items[k]);
     b->chunks_dev = (BatchChunk*)(base + o.chunks);
     b->counters = (int*)(base + o.counters);
     b->flags_dev = (int*)(base + o.flags);
-    for (dsm_sim* s : b->sims) b->present[type_index(s->p.dim)] = true;
-    b->sched[0] = dsm_batch_schedule{2, 32, 0};
+    for (dsm_sim* s : b->sims) b->present[group_of(s)] = true;
+    b->sched[0] = dsm_batch_schedule{0, 32, 0};
     b->sched[1] = dsm_batch_schedule{2, 16, 0};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -381,7 +391,7 @@ int dsm_batch_create(dsm_sim* const* sims, int count, void* dev_buf, size_t dev_
     if (e == hipSuccess) e = hipMemsetAsync(dev_buf, 0, o.total, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return cleanup(set_error(DSM_EDEVICE, std::string("dsm_batch_create: ") + hipGetErrorString(e)));
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < kGroups; ++t)
         if (b->present[t]) {
             int rc = build_items(b, t);
             if (rc) return cleanup(rc);
@@ -397,10 +407,14 @@ int dsm_batch_set_schedule(dsm_batch* b, int dim, const dsm_batch_schedule* sche
     if (dim != 2 && dim != 3) return set_error(DSM_EINVAL, "dim must be 2 or 3");
     int rc = check_sched(dim, sched);
     if (rc) return rc;
-    const int t = type_index(dim);
-    b->sched[t] = *sched;
-    if (!b->present[t]) return DSM_OK;
-    return build_items(b, t);
+    const int d = type_index(dim);
+    b->sched[d] = *sched;
+    for (int t = 2 * d; t < 2 * d + 2; ++t)
+        if (b->present[t]) {
+            rc = build_items(b, t);
+            if (rc) return rc;
+        }
+    return DSM_OK;
 }
 
 int dsm_batch_get_schedule(const dsm_batch* b, int dim, dsm_batch_schedule* sched) {
@@ -417,25 +431,26 @@ int dsm_batch_tune(dsm_batch* b, int reps, double cost[2]) {
     if (cost) cost[0] = cost[1] = 0.0;
     int rc = refresh(b);
     if (rc) return rc;
-    for (int t = 0; t < 2; ++t) {
-        if (!b->present[t]) continue;
-        const int dim = t == 0 ? 2 : 3;
-        dsm_batch_schedule best = b->sched[t];
+    for (int d = 0; d < 2; ++d) {
+        if (!b->present[2 * d] && !b->present[2 * d + 1]) continue;
+        const int dim = d == 0 ? 2 : 3;
+        dsm_batch_schedule best = b->sched[d];
         double best_cost = 1e300;
-        for (int v = 0; v < fused_tile_variants(dim); ++v) {
-            const int per_cu = batch_blocks_per_cu(dim, v, b->half);
+        for (int v = 0; v < fused_tile_variants(dim); ++v)
             for (int planes : kTunePlanes) {
-                const double c = schedule_cost(b, dim, v, planes, per_cu);
+                const double c = schedule_cost(b, dim, v, planes);
                 if (c < best_cost) {
                     best_cost = c;
                     best = dsm_batch_schedule{v, planes, 0};
                 }
             }
-        }
-        b->sched[t] = best;
-        rc = build_items(b, t);
-        if (rc) return rc;
-        if (cost) cost[t] = best_cost;
+        b->sched[d] = best;
+        for (int t = 2 * d; t < 2 * d + 2; ++t)
+            if (b->present[t]) {
+                rc = build_items(b, t);
+                if (rc) return rc;
+            }
+        if (cost) cost[d] = best_cost;
     }
     return DSM_OK;
 }
@@ -479,7 +494,10 @@ int dsm_batch_size(const dsm_batch* b) { return b ? (int)b->sims.size() : -1; }
 
 int dsm_batch_items(const dsm_batch* b, int dim) {
     if (!b || (dim != 2 && dim != 3)) return -1;
-    return b->present[type_index(dim)] ? b->nitems[type_index(dim)] : 0;
+    int n = 0;
+    for (int t = 2 * type_index(dim); t < 2 * type_index(dim) + 2; ++t)
+        if (b->present[t]) n += b->nitems[t];
+    return n;
 }
 
 int dsm_batch_destroy(dsm_batch* b) {

@@ -141,7 +141,7 @@ struct F16 {  // FP16 holding value * kHalfScale
 
 // One tile of the march: columns [x0, x0 + 64 TXW) x rows [y0, y0 + TY),
 // planes [z0, z0 + TZ) of one lattice.
-template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
+template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
 __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const void* __restrict__ fsrc,
                                            const void* __restrict__ gsrc, void* __restrict__ fdst,
                                            void* __restrict__ gdst, const float* __restrict__ c1g,
@@ -291,6 +291,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
         }
         lc *= 6.f;
         float mu, C1 = 0.f;
+        float rho = 1.f, grx = 0.f, gry = 0.f, grz = 0.f;  // local density and its gradient (contrast)
         if (STAGE == 2) {
             C1 = s_c1[s0][rint];
             float l1 = 0.f;
@@ -299,9 +300,23 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
                 const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);
                 const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);
                 const int o = L::cx[i] + CRX * L::cy[i];
-                l1 += L::w[i] * ((s_c1[spl][rint + o] - C1) + (s_c1[smi][rint - o] - C1));
+                const float a1 = s_c1[spl][rint + o], b1 = s_c1[smi][rint - o];
+                l1 += L::w[i] * ((a1 - C1) + (b1 - C1));
+                if (RHO) {
+                    const float d = local_density(ph, s_c[spl][rint + o], a1) -
+                                    local_density(ph, s_c[smi][rint - o], b1);
+                    grx += L::w[i] * L::cx[i] * d;
+                    gry += L::w[i] * L::cy[i] * d;
+                    grz += L::w[i] * L::cz[i] * d;
+                }
             }
             l1 *= 6.f;
+            if (RHO) {
+                rho = local_density(ph, C, C1);
+                grx *= 3.f;
+                gry *= 3.f;
+                grz *= 3.f;
+            }
             const float S = C1 + C;
             mu = ph.k2 * C * (1.f - C) * (1.f - 2.f * C) + ph.k3 * S * (1.f - S) * (1.f - 2.f * S) -
                  ph.a2 * ph.k2 * lc - ph.a2 * ph.k3 * (l1 + lc);
@@ -334,18 +349,42 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
             ux = mx + 0.5f * Fx;
             uy = my + 0.5f * Fy;
             uz = mz + 0.5f * Fz;
+            if (RHO) {
+                // rho u = sum c_i f_i + F/2;  p~ = sum f_i + u . grad rho / 2
+                ux /= rho;
+                uy /= rho;
+                uz /= rho;
+                pt += 0.5f * (ux * grx + uy * gry + uz * grz);
+            }
         }
         const float uu = ux * ux + uy * uy + uz * uz;
         const unsigned own_off = ES * (unsigned)(yv[1] * QX);
         if (!solid) {
             const __amdgpu_buffer_rsrc_t fo = plane_rsrc(fdst, PL, c);
+            float itau = ph.inv_tau, fp3 = fpref3, ug = 0.f;
+            if (RHO) {
+                // tau = tau_3 + (tau_2 - tau_3) H(C2 - C3)
+                const bool liquid = C - (1.f - C1 - C) > 0.f;
+                itau = liquid ? ph.inv_tau : ph.inv_tau3;
+                fp3 = liquid ? fpref3 : 3.f * ph.fpref_gas;
+                ug = ux * grx + uy * gry + uz * grz;
+            }
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
                 const float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
-                const float feq = L::w[i] * (pt + s_i(cu, uu));
-                E::store(fo, xb[1], own_off + ES * (unsigned)(i * X),
-                         f[i] - (f[i] - feq) * ph.inv_tau + fpref3 * L::w[i] * cF);
+                const float si = s_i(cu, uu);
+                float feq, fi;
+                if (RHO) {
+                    // F_i = (1 - 1/2tau) w_i [((c_i - u) . grad rho) s_i + c_i . F / c_s^2]
+                    const float cg = L::cx[i] * grx + L::cy[i] * gry + L::cz[i] * grz - ug;
+                    feq = L::w[i] * (pt + rho * si);
+                    fi = fp3 * L::w[i] * (cF + (1.f / 3.f) * cg * si);
+                } else {
+                    feq = L::w[i] * (pt + si);
+                    fi = fp3 * L::w[i] * cF;
+                }
+                E::store(fo, xb[1], own_off + ES * (unsigned)(i * X), f[i] - (f[i] - feq) * itau + fi);
             }
         }
         const __amdgpu_buffer_rsrc_t go = plane_rsrc(gdst, PL, c);
@@ -371,7 +410,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
     }
 }
 
-template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
+template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
 __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
     k_step_fused(Geom g, Phys ph, const void* __restrict__ fsrc, const void* __restrict__ gsrc,
                  void* __restrict__ fdst, void* __restrict__ gdst, const float* __restrict__ c1g,
@@ -384,18 +423,19 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
     const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
     const int tile_x = tile % ntx, rest = tile / ntx;
     const int tile_y = rest % nty, tile_z = rest / nty;
-    fused_tile<D, TXW, TY, STAGE, PULL, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, tile_x * TX, tile_y * TY,
-                                           tile_z * TZ, TZ);
+    fused_tile<D, TXW, TY, STAGE, PULL, RHO, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, tile_x * TX,
+                                                tile_y * TY, tile_z * TZ, TZ);
 }
 
-// Batched step: many lattices (same lattice type and storage) advance in one
+// Batched step: many lattices (same lattice type, storage and contrast
+// variant) advance in one
 // persistent launch.  The work list holds (lattice, tile) items, costliest
 // first; each workgroup takes the next item from a shared counter (reset to
 // zero by the bounce kernel that precedes every batched step) until the list
 // is drained, so uneven lattices balance over the chip.  Each lattice's
 // geometry, parameters and buffers come from a descriptor table, with the
 // two buffer pairs exchanged by the step parity.
-template <int D, int TXW, int TY, typename E>
+template <int D, int TXW, int TY, bool RHO, typename E>
 __global__ void __launch_bounds__(64 * TXW * TY)
     k_step_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems,
                  int* __restrict__ counter, int parity, int TZ) {
@@ -407,13 +447,13 @@ __global__ void __launch_bounds__(64 * TXW * TY)
         if (it >= nitems) break;  // uniform over the workgroup
         const BatchItem w = items[it];
         const BatchInst& d = inst[w.inst];
-        fused_tile<D, TXW, TY, 2, true, E>(d.geom, d.phys, d.f[parity], d.g[parity], d.f[1 - parity],
-                                           d.g[1 - parity], d.c1, d.mask, d.flag, w.x0, w.y0, w.z0, TZ);
+        fused_tile<D, TXW, TY, 2, true, RHO, E>(d.geom, d.phys, d.f[parity], d.g[parity], d.f[1 - parity],
+                                                d.g[1 - parity], d.c1, d.mask, d.flag, w.x0, w.y0, w.z0, TZ);
         __syncthreads();  // s_item is rewritten only after every wave has read it
     }
 }
 
-template <int D, int TXW, int TY, int STAGE, bool PULL, typename E>
+template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
 hipError_t launch_cfg(const Geom& g, const Phys& ph, const void* fsrc, const void* gsrc, void* fdst, void* gdst,
                       const float* c1, const uint8_t* mask, int* flag, int TZ, hipStream_t st) {
     constexpr int TX = 64 * TXW;
@@ -422,7 +462,7 @@ hipError_t launch_cfg(const Geom& g, const Phys& ph, const void* fsrc, const voi
     const int ntz = (g.Z + TZ - 1) / TZ;
     const long long nblocks = (long long)ntx * nty * ntz;
     if (nblocks < 1 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step_fused<D, TXW, TY, STAGE, PULL, E>), dim3((unsigned)nblocks), dim3(64 * TXW * TY), 0,
+    hipLaunchKernelGGL((k_step_fused<D, TXW, TY, STAGE, PULL, RHO, E>), dim3((unsigned)nblocks), dim3(64 * TXW * TY), 0,
                        st, g, ph, fsrc, gsrc, fdst, gdst, c1, mask, flag, TZ, ntx, nty);
     return hipGetLastError();
 }
@@ -430,13 +470,18 @@ hipError_t launch_cfg(const Geom& g, const Phys& ph, const void* fsrc, const voi
 template <int D, int TXW, int TY, typename E>
 hipError_t launch_tile_e(const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst, const float* c1,
                          const uint8_t* mask, int pull, int* flag, int TZ, hipStream_t st) {
-    if (ph.stage == 2) {
-        if (pull)
-            return launch_cfg<D, TXW, TY, 2, true, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
-        return launch_cfg<D, TXW, TY, 2, false, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
+    const void *fs = fsrc.p, *gs = gsrc.p;
+    void *fd = fdst.p, *gd = gdst.p;
+    if (ph.stage == 2 && ph.contrast) {
+        if (pull) return launch_cfg<D, TXW, TY, 2, true, true, E>(g, ph, fs, gs, fd, gd, c1, mask, flag, TZ, st);
+        return launch_cfg<D, TXW, TY, 2, false, true, E>(g, ph, fs, gs, fd, gd, c1, mask, flag, TZ, st);
     }
-    if (pull) return launch_cfg<D, TXW, TY, 1, true, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
-    return launch_cfg<D, TXW, TY, 1, false, E>(g, ph, fsrc.p, gsrc.p, fdst.p, gdst.p, c1, mask, flag, TZ, st);
+    if (ph.stage == 2) {
+        if (pull) return launch_cfg<D, TXW, TY, 2, true, false, E>(g, ph, fs, gs, fd, gd, c1, mask, flag, TZ, st);
+        return launch_cfg<D, TXW, TY, 2, false, false, E>(g, ph, fs, gs, fd, gd, c1, mask, flag, TZ, st);
+    }
+    if (pull) return launch_cfg<D, TXW, TY, 1, true, false, E>(g, ph, fs, gs, fd, gd, c1, mask, flag, TZ, st);
+    return launch_cfg<D, TXW, TY, 1, false, false, E>(g, ph, fs, gs, fd, gd, c1, mask, flag, TZ, st);
 }
 
 template <int D, int TXW, int TY>
@@ -448,33 +493,45 @@ hipError_t launch_tile(const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fd
 
 }  // namespace
 
-template <int D, int TXW, int TY, typename E>
+template <int D, int TXW, int TY, bool RHO, typename E>
 auto batch_kernel() {
-    return k_step_batch<D, TXW, TY, E>;
+    return k_step_batch<D, TXW, TY, RHO, E>;
 }
 
-template <int D, int TXW, int TY>
-hipError_t launch_batch_tile(const BatchInst* inst, const BatchItem* items, int nitems, int* counter, int grid,
-                             int parity, int TZ, int half, hipStream_t st) {
-    if (nitems <= 0) return hipSuccess;
-    const int blocks = grid < nitems ? grid : nitems;
+template <int D, int TXW, int TY, bool RHO>
+hipError_t launch_batch_rho(const BatchInst* inst, const BatchItem* items, int nitems, int* counter, int blocks,
+                            int parity, int TZ, int half, hipStream_t st) {
     if (half)
-        hipLaunchKernelGGL((k_step_batch<D, TXW, TY, F16>), dim3(blocks), dim3(64 * TXW * TY), 0, st, inst, items,
-                           nitems, counter, parity, TZ);
+        hipLaunchKernelGGL((k_step_batch<D, TXW, TY, RHO, F16>), dim3(blocks), dim3(64 * TXW * TY), 0, st, inst,
+                           items, nitems, counter, parity, TZ);
     else
-        hipLaunchKernelGGL((k_step_batch<D, TXW, TY, F32>), dim3(blocks), dim3(64 * TXW * TY), 0, st, inst, items,
-                           nitems, counter, parity, TZ);
+        hipLaunchKernelGGL((k_step_batch<D, TXW, TY, RHO, F32>), dim3(blocks), dim3(64 * TXW * TY), 0, st, inst,
+                           items, nitems, counter, parity, TZ);
     return hipGetLastError();
 }
 
 template <int D, int TXW, int TY>
-int batch_occupancy_tile(int half) {
+hipError_t launch_batch_tile(const BatchInst* inst, const BatchItem* items, int nitems, int* counter, int grid,
+                             int parity, int TZ, int half, int rho, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = grid < nitems ? grid : nitems;
+    if (rho) return launch_batch_rho<D, TXW, TY, true>(inst, items, nitems, counter, blocks, parity, TZ, half, st);
+    return launch_batch_rho<D, TXW, TY, false>(inst, items, nitems, counter, blocks, parity, TZ, half, st);
+}
+
+template <int D, int TXW, int TY, bool RHO>
+int batch_occupancy_rho(int half) {
     int n = 0;
-    hipError_t e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<D, TXW, TY, F16>(),
+    hipError_t e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<D, TXW, TY, RHO, F16>(),
                                                                       64 * TXW * TY, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<D, TXW, TY, F32>(),
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<D, TXW, TY, RHO, F32>(),
                                                                       64 * TXW * TY, 0);
     return e == hipSuccess && n > 0 ? n : 1;
+}
+
+template <int D, int TXW, int TY>
+int batch_occupancy_tile(int half, int rho) {
+    return rho ? batch_occupancy_rho<D, TXW, TY, true>(half) : batch_occupancy_rho<D, TXW, TY, false>(half);
 }
 
 int fused_tile_variants(int dim) { return 3; }
@@ -487,35 +544,35 @@ void fused_tile_shape(int dim, int variant, int* tx, int* ty) {
     *ty = dim == 2 ? t2[v][1] : t3[v][1];
 }
 
-hipError_t launch_step_batch(int dim, int variant, int half, const BatchInst* inst, const BatchItem* items,
+hipError_t launch_step_batch(int dim, int variant, int half, int rho, const BatchInst* inst, const BatchItem* items,
                              int nitems, int* counter, int grid, int parity, int TZ, hipStream_t st) {
     if (TZ < 1) TZ = 1;
     if (dim == 2) {
         switch (variant) {
-            case 1: return launch_batch_tile<2, 2, 1>(inst, items, nitems, counter, grid, parity, TZ, half, st);
-            case 2: return launch_batch_tile<2, 1, 1>(inst, items, nitems, counter, grid, parity, TZ, half, st);
-            default: return launch_batch_tile<2, 4, 1>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+            case 1: return launch_batch_tile<2, 2, 1>(inst, items, nitems, counter, grid, parity, TZ, half, rho, st);
+            case 2: return launch_batch_tile<2, 1, 1>(inst, items, nitems, counter, grid, parity, TZ, half, rho, st);
+            default: return launch_batch_tile<2, 4, 1>(inst, items, nitems, counter, grid, parity, TZ, half, rho, st);
         }
     }
     switch (variant) {
-        case 1: return launch_batch_tile<3, 1, 8>(inst, items, nitems, counter, grid, parity, TZ, half, st);
-        case 2: return launch_batch_tile<3, 2, 4>(inst, items, nitems, counter, grid, parity, TZ, half, st);
-        default: return launch_batch_tile<3, 1, 4>(inst, items, nitems, counter, grid, parity, TZ, half, st);
+        case 1: return launch_batch_tile<3, 1, 8>(inst, items, nitems, counter, grid, parity, TZ, half, rho, st);
+        case 2: return launch_batch_tile<3, 2, 4>(inst, items, nitems, counter, grid, parity, TZ, half, rho, st);
+        default: return launch_batch_tile<3, 1, 4>(inst, items, nitems, counter, grid, parity, TZ, half, rho, st);
     }
 }
 
-int batch_blocks_per_cu(int dim, int variant, int half) {
+int batch_blocks_per_cu(int dim, int variant, int half, int rho) {
     if (dim == 2) {
         switch (variant) {
-            case 1: return batch_occupancy_tile<2, 2, 1>(half);
-            case 2: return batch_occupancy_tile<2, 1, 1>(half);
-            default: return batch_occupancy_tile<2, 4, 1>(half);
+            case 1: return batch_occupancy_tile<2, 2, 1>(half, rho);
+            case 2: return batch_occupancy_tile<2, 1, 1>(half, rho);
+            default: return batch_occupancy_tile<2, 4, 1>(half, rho);
         }
     }
     switch (variant) {
-        case 1: return batch_occupancy_tile<3, 1, 8>(half);
-        case 2: return batch_occupancy_tile<3, 2, 4>(half);
-        default: return batch_occupancy_tile<3, 1, 4>(half);
+        case 1: return batch_occupancy_tile<3, 1, 8>(half, rho);
+        case 2: return batch_occupancy_tile<3, 2, 4>(half, rho);
+        default: return batch_occupancy_tile<3, 1, 4>(half, rho);
     }
 }
 

@@ -114,9 +114,9 @@ hipError_t launch_bounce(Pop f, const LinkRec* rec, int count, hipStream_t st);
 // bounce-back slots of fsrc must have been written by launch_bounce.
 int fused_tile_variants(int dim);
 void fused_tile_shape(int dim, int variant, int* tx, int* ty);
-hipError_t launch_step_batch(int dim, int variant, int half, const BatchInst* inst, const BatchItem* items,
+hipError_t launch_step_batch(int dim, int variant, int half, int rho, const BatchInst* inst, const BatchItem* items,
                              int nitems, int* counter, int grid, int parity, int TZ, hipStream_t st);
-int batch_blocks_per_cu(int dim, int variant, int half);
+int batch_blocks_per_cu(int dim, int variant, int half, int rho);
 hipError_t launch_bounce_batch(const BatchInst* inst, const BatchChunk* chunks, int nchunks, int parity,
                                int* counters, int ncounters, hipStream_t st);
 hipError_t launch_batch_flags(const BatchInst* inst, int count, int* out, hipStream_t st);

@@ -65,6 +65,25 @@ __device__ __forceinline__ void gradient(const Geom& g, const float* a, int x, i
 
 __device__ __forceinline__ float s_i(float cu, float uu) { return 3.f * cu + 4.5f * cu * cu - 1.5f * uu; }
 
+// G[rho](x) for the local density of the fluid stage, from C2 = phi and C1
+template <int D>
+__device__ __forceinline__ void density_gradient(const Geom& g, const Phys& ph, const float* phi, const float* c1,
+                                                 int x, int y, int z, float out[3]) {
+    using L = Lattice<D>;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int i = 1; i < L::Q; i += 2) {
+        const long long a = shifted<D>(g, x, y, z, i, +1), b = shifted<D>(g, x, y, z, i + 1, +1);
+        const float d = local_density(ph, phi[a], c1[a]) - local_density(ph, phi[b], c1[b]);
+        gx += L::w[i] * L::cx[i] * d;
+        gy += L::w[i] * L::cy[i] * d;
+        gz += L::w[i] * L::cz[i] * d;
+    }
+    out[0] = 3.f * gx;
+    out[1] = 3.f * gy;
+    out[2] = 3.f * gz;
+}
+
 // Wall fraction of the link from fluid node n along direction k, from the
 // tanh profile of the diffuse solid (Sec. II.B).  FP64: it is evaluated only
 // on links that cross the solid boundary.
@@ -220,6 +239,7 @@ __global__ void k_collide(Geom g, Phys ph, Pop fsrc, Pop gsrc,
     const bool solid = ph.stage == 2 && c1[n] > 0.5f;
     float ux = 0.f, uy = 0.f, uz = 0.f, pt = 0.f;
     float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    float rho = 1.f, gr[3] = {0.f, 0.f, 0.f};
     float f[Q];
     if (!solid) {
         // surface tension in the potential form mu grad C, plus the body force
@@ -256,6 +276,15 @@ __global__ void k_collide(Geom g, Phys ph, Pop fsrc, Pop gsrc,
         ux = mx + 0.5f * Fx;
         uy = my + 0.5f * Fy;
         uz = mz + 0.5f * Fz;
+        if (ph.contrast) {
+            // rho u = sum c_i f_i + F/2;  p~ = sum f_i + u . grad rho / 2
+            rho = local_density(ph, C, c1[n]);
+            density_gradient<D>(g, ph, phi, c1, x, y, z, gr);
+            ux /= rho;
+            uy /= rho;
+            uz /= rho;
+            pt += 0.5f * (ux * gr[0] + uy * gr[1] + uz * gr[2]);
+        }
     }
     if (MODE == 1) {
         // stored axes -> user axes: 2D uses (x, z) as (x, y)
@@ -274,13 +303,19 @@ __global__ void k_collide(Geom g, Phys ph, Pop fsrc, Pop gsrc,
 #pragma unroll
         for (int i = 0; i < Q; ++i) fdst.st(pop_index(g, L::Q, i, n), 0.f);
     } else {
+        // tau = tau_3 + (tau_2 - tau_3) H(C2 - C3) under contrast
+        const bool gas = ph.contrast && !(C - (1.f - c1[n] - C) > 0.f);
+        const float itau = gas ? ph.inv_tau3 : ph.inv_tau, fpref = gas ? ph.fpref_gas : ph.fpref;
+        const float ug = ux * gr[0] + uy * gr[1] + uz * gr[2];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
             float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
-            float feq = L::w[i] * (pt + s_i(cu, uu));
-            float Fi = ph.fpref * L::w[i] * 3.f * cF;
-            fdst.st(pop_index(g, L::Q, i, n), f[i] - (f[i] - feq) * ph.inv_tau + Fi);
+            float si = s_i(cu, uu);
+            float feq = L::w[i] * (pt + rho * si);
+            float cg = L::cx[i] * gr[0] + L::cy[i] * gr[1] + L::cz[i] * gr[2] - ug;
+            float Fi = fpref * L::w[i] * (3.f * cF + cg * si);
+            fdst.st(pop_index(g, L::Q, i, n), f[i] - (f[i] - feq) * itau + Fi);
         }
     }
     const float m = mu[n];
@@ -430,7 +465,8 @@ __global__ void __launch_bounds__(kBlock) k_reduce(Geom g, Phys ph, const float*
         double ux = aux[n], uy = aux[N + n], uz = D == 3 ? (double)aux[2 * N + n] : 0.0;
         double uu = ux * ux + uy * uy + uz * uz;
         bool solid = ph.stage == 2 && c1[n] > 0.5f;
-        if (!solid) acc[RED_EKIN] += 0.5 * uu;
+        const double rho = ph.contrast ? (double)local_density(ph, phi[n], c1[n]) : 1.0;
+        if (!solid) acc[RED_EKIN] += 0.5 * rho * uu;
         double um = sqrt(uu);
         if (!(um <= acc[RED_UMAX])) acc[RED_UMAX] = isfinite(um) ? um : acc[RED_UMAX];
         if (!isfinite(C2) || !isfinite(C1) || !isfinite(uu)) acc[RED_NONFINITE] += 1.0;

@@ -62,7 +62,20 @@ struct Phys {
     float grav[3];       // body force per unit liquid (stored axes)
     float beta, omega;   // solid stage
     int stage;           // 1 = solid stage (C1 evolves), 2 = fluid stage (C2 evolves)
+    // density and viscosity contrast of the fluid stage: rho_2, rho_3, and
+    // for the gas side (C2 <= C3) 1/tau_3 and 1 - 1/(2 tau_3)
+    float rho2, rho3;
+    float inv_tau3, fpref_gas;
+    int contrast;        // 1: any of rho_2, rho_3 != 1 or tau_3 != tau
 };
+
+// Local density of the fluid stage, rho_3 + (rho_2 - rho_3) C2 / (C2 + C3)
+// with C2 + C3 = 1 - C1 floored at 1e-6 and the fraction clamped to [0, 1].
+__device__ __forceinline__ float local_density(const Phys& ph, float C2, float C1) {
+    const float den = fmaxf(1.f - C1, 1e-6f);
+    const float frac = fminf(fmaxf(C2 / den, 0.f), 1.f);
+    return ph.rho3 + (ph.rho2 - ph.rho3) * frac;
+}
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 

@@ -42,6 +42,7 @@ class dsm_params(ctypes.Structure):
         ("kappa", ctypes.c_double * 3), ("alpha", ctypes.c_double), ("tau", ctypes.c_double),
         ("mobility", ctypes.c_double), ("gravity", ctypes.c_double * 3),
         ("reduce_every", ctypes.c_int), ("kernel", ctypes.c_int), ("storage", ctypes.c_int),
+        ("rho", ctypes.c_double * 2), ("tau_gas", ctypes.c_double),
     ]
 
 
@@ -130,7 +131,8 @@ def _f64(a):
 # one function per C entry point
 
 def make_params(dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
-                reduce_every=0, kernel=DSM_KERNEL_FUSED, storage=DSM_STORAGE_FP32) -> dsm_params:
+                reduce_every=0, kernel=DSM_KERNEL_FUSED, storage=DSM_STORAGE_FP32, rho=(1.0, 1.0),
+                tau_gas=0.0) -> dsm_params:
     p = dsm_params()
     p.dim = int(dim)
     p.nx, p.ny = int(shape[0]), int(shape[1])
@@ -140,6 +142,8 @@ def make_params(dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.
     g = list(gravity) + [0.0] * (3 - len(gravity))
     p.gravity[:] = [float(v) for v in g]
     p.reduce_every, p.kernel, p.storage = int(reduce_every), int(kernel), int(storage)
+    p.rho[:] = [float(rho[0]), float(rho[1])]
+    p.tau_gas = float(tau_gas or 0.0)
     return p
 
 
@@ -335,7 +339,7 @@ class Simulation:
 
     def __init__(self, dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1, gravity=(0.0, 0.0, 0.0),
                  mask=None, reduce_every=0, kernel=DSM_KERNEL_FUSED, storage=DSM_STORAGE_FP32, device="cuda:0",
-                 stream=None, dev_ptr=None):
+                 stream=None, dev_ptr=None, rho=(1.0, 1.0), tau_gas=0.0):
         """dev_ptr: optional 256-byte aligned device address of at least
         dsm_required_bytes bytes that the caller owns (e.g. a block of a
         larger arena); by default a torch buffer is allocated."""
@@ -343,7 +347,8 @@ class Simulation:
 
         self.dim = dim
         self.shape = tuple(shape)
-        self.params = make_params(dim, shape, kappa, alpha, tau, mobility, gravity, reduce_every, kernel, storage)
+        self.params = make_params(dim, shape, kappa, alpha, tau, mobility, gravity, reduce_every, kernel, storage,
+                                  rho, tau_gas)
         self.N = int(self.params.nx * self.params.ny * self.params.nz)
         self.Q = 9 if dim == 2 else 19
         self.nbytes = dsm_required_bytes(self.params)

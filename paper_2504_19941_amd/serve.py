@@ -319,7 +319,7 @@ class GpuExecutor:
     def _params(self, job):
         w = job.workload
         return self.dsm.make_params(w.dim, w.shape, w.kappa, w.alpha, w.tau, w.mobility, w.gravity,
-                                    storage=job.storage)
+                                    storage=job.storage, rho=w.rho, tau_gas=w.tau_gas or 0.0)
 
     def job_bytes(self, job) -> int:
         return self.dsm.dsm_required_bytes(self._params(job))
@@ -331,7 +331,7 @@ class GpuExecutor:
         f32 = lambda a: W.flat(np.asarray(a, dtype=np.float32).astype(np.float64))  # noqa: E731
         sim = self.dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
                                   gravity=w.gravity, storage=job.storage, device=self.device,
-                                  dev_ptr=self.base + offset)
+                                  dev_ptr=self.base + offset, rho=w.rho, tau_gas=w.tau_gas or 0.0)
         sim.set_solid_field(f32(w.C1))
         sim.set_liquid(f32(w.C2))
         sim.step(1)  # the first step reads at-node populations; later steps run batched

@@ -109,6 +109,8 @@ class Workload:
     wall_axis: int = 1
     solid_stage: dict = field(default_factory=dict)
     seed: int = 0
+    rho: tuple = (1.0, 1.0)             # densities of liquid and gas
+    tau_gas: float | None = None        # relaxation time of the gas (None: tau)
 
     @property
     def nodes(self) -> int:
@@ -244,7 +246,7 @@ def batch_2d_sinusoid(count: int = 512, seed: int = 4, size_lo=(64, 32), size_hi
 
 
 def capillary_channel(width: int, length: int, theta_deg: float, gravity: float, wall: int = 4,
-                      alpha: float = 1.0, seed: int = 0) -> Workload:
+                      alpha: float = 1.0, seed: int = 0, tau: float = 1.0, tau_gas: float = 0.52) -> Workload:
     """D3Q19 capillary filling: a square duct of ``width`` nodes (walls
     ``wall`` thick on each side, so the periodic box is width + 2 wall
     across) along x, fed from a liquid reservoir.  The duct axis is the
@@ -253,7 +255,9 @@ def capillary_channel(width: int, length: int, theta_deg: float, gravity: float,
     the duct starts at xr = length / 4, and the liquid fills the reservoir up
     to xr + 2.  Gravity -g along x.  C1 is the tanh profile of the signed
     distance to the solid (union of duct walls and end plate, each a max/min
-    of plane distances)."""
+    of plane distances).  The default relaxation times give the kinematic
+    viscosities 1/6 (liquid) and 2/300 (gas) of the paper's capillary-filling
+    runs, at equal densities."""
     n = width + 2 * wall
     shape = (length, n, n)
     X, Y, Z = _coords(shape)
@@ -267,7 +271,7 @@ def capillary_channel(width: int, length: int, theta_deg: float, gravity: float,
     C2 = liquid * (1.0 - C1)
     return Workload(name=f"d3q19-channel-w{width}-L{length}-theta{theta_deg:.0f}", dim=3, shape=shape,
                     kappa=kappas_for_angle(theta_deg), alpha=alpha, mask=(C1 > 0.5).astype(np.uint8),
-                    C1=C1, C2=C2, gravity=(-gravity, 0.0, 0.0), seed=seed)
+                    C1=C1, C2=C2, gravity=(-gravity, 0.0, 0.0), seed=seed, tau=tau, tau_gas=tau_gas)
 
 
 def particle_at_interface(n: int, radius: float, theta_deg: float, alpha: float = 1.0,
@@ -289,8 +293,8 @@ def particle_at_interface(n: int, radius: float, theta_deg: float, alpha: float 
 
 
 SERVE_RECIPE = ("Poisson arrivals; half capillary-filling jobs (square duct width 8-32, length 128-512, "
-                "gravity 1e-6-1e-5, theta 30-80 deg), half particle-at-interface jobs (n^3 box n 96-160, "
-                "particle radius 10-20, theta 45-135 deg)")
+                "gravity 1e-6-1e-5, theta 30-80 deg, liquid/gas viscosity 1/6 vs 2/300), half "
+                "particle-at-interface jobs (n^3 box n 96-160, particle radius 10-20, theta 45-135 deg)")
 
 
 def serve_jobs(count: int, seed: int = 5, steps=(200, 1000), small: bool = False) -> list:

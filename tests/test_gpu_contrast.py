@@ -1,0 +1,149 @@
+"""Density and viscosity contrast on the GPU (Sec. II.B: rho = rho_3 +
+(rho_2 - rho_3) C2 / (C2 + C3), tau = tau_3 + (tau_2 - tau_3) H(C2 - C3)):
+1000 FP32 steps against the FP64 oracle, the fused kernel against the
+three-kernel step, the exact acceleration of a uniform mixture, the
+closed-form two-layer channel profile, and a batch mixing uniform and
+contrast lattices that reproduces each run alone bit for bit."""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2504_19941_amd import dsm
+from paper_2504_19941_amd import workloads as W
+
+from .conftest import f32
+from .geometry import wall_and_particle
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = W.kappas_for_angle(70.0)
+RHO = (1.0, 0.5)
+TAU2, TAU3 = 1.0, 0.7
+
+
+def report(name, a, b):
+    err = float(np.abs(np.asarray(a) - np.asarray(b)).max())
+    print(f"  {name}: max abs err {err:.3e}", flush=True)
+    return err
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (150, 37)), (3, (40, 21, 35))])
+def test_1000_steps_match_oracle(gpu, dim, shape):
+    mask, C1, C2 = wall_and_particle(dim, shape, seed=161)
+    C1, C2 = f32(W.flat(C1)), f32(W.flat(C2))
+    grav = (1e-5, -2e-6, 0.0) if dim == 2 else (1e-5, 3e-6, -2e-6)
+    sim = dsm.Simulation(dim, shape, KAPPA, tau=TAU2, gravity=grav, rho=RHO, tau_gas=TAU3, reduce_every=250)
+    orc = Oracle(dim, shape, KAPPA, tau=TAU2, gravity=grav, rho=RHO, tau_gas=TAU3, threads=8)
+    for s in (sim, orc):
+        s.set_solid_field(C1)
+        s.set_liquid(C2)
+    m0 = sim.mass()
+    for s in (sim, orc):
+        s.step(1000)
+    fg, fo = sim.fields(), orc.fields()
+    assert report("C2", fg["C2"], fo["C2"]) < 1e-5
+    assert report("u", fg["u"], fo["u"]) < 1e-6
+    assert report("p", fg["p"], fo["p"]) < 1e-6
+    assert np.abs(fo["u"]).max() > 1e-5  # a flow that exercises the contrast terms
+    m1 = sim.mass()
+    assert abs(m1[1] - m0[1]) / m0[1] < 1e-9
+    F, E = sim.free_energy()
+    Fo, Eo = orc.free_energy()
+    print(f"  free energy {F:.9e} vs {Fo:.9e}, kinetic {E:.6e} vs {Eo:.6e}", flush=True)
+    assert abs(F - Fo) <= 1e-6 * abs(Fo) and abs(E - Eo) <= 1e-3 * Eo
+    orc.close()
+
+
+def test_fused_matches_split(gpu):
+    shape = (64, 40, 36)
+    mask, C1, C2 = wall_and_particle(3, shape, seed=141)
+    res = []
+    for kernel in (dsm.DSM_KERNEL_FUSED, dsm.DSM_KERNEL_SPLIT):
+        sim = dsm.Simulation(3, shape, KAPPA, tau=TAU2, kernel=kernel, rho=RHO, tau_gas=TAU3,
+                             gravity=(0.0, 2e-6, 0.0))
+        sim.set_solid_field(W.flat(C1))
+        sim.set_liquid(W.flat(C2))
+        sim.step(200)
+        res.append(sim.fields())
+    assert report("C2", res[0]["C2"], res[1]["C2"]) < 1e-6
+    assert report("u", res[0]["u"], res[1]["u"]) < 1e-7
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (70, 6)), (3, (70, 5, 6))])
+def test_uniform_mixture_acceleration(gpu, dim, shape):
+    """u_n = (n + 1/2) C2 g / rho(C) exactly in exact arithmetic (FP32 here)."""
+    N = int(np.prod(shape))
+    g = np.array((2e-6, -1e-6, 3e-6)[:dim] + (0.0,) * (3 - dim))
+    r2, r3, C1, C2 = 2.5, 0.7, 0.2, 0.3
+    rho = r3 + (r2 - r3) * C2 / (1.0 - C1)
+    sim = dsm.Simulation(dim, shape, (0.01, 0.006, 0.008), gravity=g, rho=(r2, r3), tau_gas=0.8)
+    sim.set_solid_field(np.full(N, C1))
+    sim.set_liquid(np.full(N, C2))
+    sim.step(9)
+    u = sim.fields()["u"]
+    for d in range(dim):
+        assert np.allclose(u[d], 9.5 * C2 * g[d] / rho, rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("tau2,tau3,rho,tol", [(1.0, 0.6, (1.0, 1.0), 0.03), (1.0, 1.0, (1.0, 0.25), 0.08)])
+def test_two_layer_channel_flow(gpu, tau2, tau3, rho, tol):
+    """The closed-form two-layer profile (as in the oracle's pin), and the
+    oracle itself, after 16000 FP32 steps."""
+    nx, ny, wall, g = 4, 48, 4, 1e-6
+    shape = (nx, ny)
+    _, Y = np.meshgrid(np.arange(nx, dtype=float), np.arange(ny, dtype=float), indexing="ij")
+    C1 = W.tanh_profile(W.periodic_slab_distance(Y, -0.5, wall - 0.5, ny))
+    lo, hi = wall - 0.5, ny - 0.5
+    C2 = W.tanh_profile(0.5 * (lo + hi) - Y) * (1 - C1)
+    C1, C2 = f32(W.flat(C1)), f32(W.flat(C2))
+    k = W.kappas_for_angle(90.0)
+    sim = dsm.Simulation(2, shape, k, tau=tau2, gravity=(g, 0, 0), rho=rho, tau_gas=tau3)
+    orc = Oracle(2, shape, k, tau=tau2, gravity=(g, 0, 0), rho=rho, tau_gas=tau3)
+    for s in (sim, orc):
+        s.set_solid_field(C1)
+        s.set_liquid(C2)
+        s.step(16000)
+    fg, fo = sim.fields(), orc.fields()
+    u = fg["u"][0].reshape(shape, order="F")[0]
+    s = (fg["C2"] - fg["C3"]).reshape(shape, order="F")[0]
+    y = np.flatnonzero((s[wall:-1] > 0) & (s[wall + 1:] <= 0))[0] + wall
+    hl = y + s[y] / (s[y] - s[y + 1]) - lo
+    H = hi - lo
+    eta2, eta3 = rho[0] * (tau2 - 0.5) / 3, rho[1] * (tau3 - 0.5) / 3
+    A = (g * hl * (H - hl) / eta3 + g * hl * hl / (2 * eta2)) / (hl + eta2 * (H - hl) / eta3)
+    B = (g * hl - eta2 * A) / eta3
+    yy = np.arange(ny) - lo
+    ua = np.where(yy < hl, -g * yy ** 2 / (2 * eta2) + A * yy, B * (H - yy))
+    fluid = (yy > 0) & (yy < H)
+    err = np.abs(u - ua)[fluid].max() / np.abs(ua).max()
+    print(f"  closed form: rel err {err:.3e}", flush=True)
+    assert err < tol
+    assert report("u vs oracle", fg["u"], fo["u"]) < 1e-3 * np.abs(fo["u"]).max()
+    orc.close()
+
+
+def test_batch_with_contrast_members_matches_single_runs(gpu):
+    specs = [(2, (100, 37), None), (2, (64, 32), (RHO, TAU3)), (3, (40, 21, 35), (RHO, TAU3)),
+             (3, (33, 9, 12), None), (2, (129, 70), ((1.0, 1.0), 0.6))]
+
+    def make():
+        sims = []
+        for k, (dim, shape, con) in enumerate(specs):
+            mask, C1, C2 = wall_and_particle(dim, shape, seed=700 + k)
+            kw = {} if con is None else dict(rho=con[0], tau_gas=con[1])
+            s = dsm.Simulation(dim, shape, KAPPA, gravity=(1e-5, 0.0, 0.0), **kw)
+            s.set_solid_field(f32(W.flat(C1)))
+            s.set_liquid(f32(W.flat(C2)))
+            s.step(1)
+            sims.append(s)
+        return sims
+
+    A, B = make(), make()
+    batch = dsm.Batch(A)
+    batch.tune()
+    batch.step(13)
+    for s in B:
+        s.step(13)
+    for k, (a, b) in enumerate(zip(A, B)):
+        assert a.get_state() == b.get_state(), f"member {k} {specs[k]} differs from its run alone"
+    batch.close()

@@ -1,5 +1,6 @@
-"""Served form on the GPU: jobs of both kinds (capillary ducts, particles at
-an interface; FP32 and FP16 storage) submitted while others run, admitted by
+"""Served form on the GPU: jobs of both kinds (capillary ducts with the
+paper's liquid/gas viscosity contrast, particles at an interface; FP32 and
+FP16 storage) submitted while others run, admitted by
 footprint into one device arena, advanced together by the batched step, give
 exactly the result each gives alone."""
 import numpy as np
@@ -17,7 +18,7 @@ pytestmark = pytest.mark.gpu
 def alone(job):
     w = job.workload
     sim = dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
-                         gravity=w.gravity, storage=job.storage)
+                         gravity=w.gravity, storage=job.storage, rho=w.rho, tau_gas=w.tau_gas or 0.0)
     sim.set_solid_field(f32(W.flat(w.C1)))
     sim.set_liquid(f32(W.flat(w.C2)))
     sim.step(job.steps)
