@@ -61,10 +61,11 @@ def bytes_per_launch(Q: int, pop_bytes: int, fluid_nodes: int, solid_nodes: int)
     return fluid_nodes * bytes_per_node(Q, pop_bytes, False) + solid_nodes * bytes_per_node(Q, pop_bytes, True)
 
 
-def measured_traffic(workload: str, nodes: int):
+def measured_traffic(workload: str, nodes: int, tag: str = ""):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the factor measured on
-    a plain copy kernel), or None if absent or taken on other kernel source."""
+    a plain copy kernel; tag "" for FP32 storage, "_fp16" for FP16), or None
+    if absent or taken on other kernel source."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     text = open(PMC_SUMMARY).read()
@@ -76,7 +77,7 @@ def measured_traffic(workload: str, nodes: int):
     if field("workload") != workload or field("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(field("hbm_bytes_per_launch"))
+        return float(field("hbm_bytes_per_launch" + tag))
     except (TypeError, ValueError):
         return None
 
@@ -400,6 +401,7 @@ def main():
         "hbm_frac": round(r16["achieved"] / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes": r16["alg_bytes"],
         "speedup_vs_fp32": round(r16["mlups"] / r32["mlups"], 3),
+        "traffic": measured_traffic(w.name, N, "_fp16"),
         "liquid_mass_drift_rel": r16["drift"],
     }
     if not args.no_batch:
