@@ -306,6 +306,7 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="offered load: arrival rate x mean job work / --serve-capacity-lups")
     ap.add_argument("--serve-capacity-lups", type=float, default=12e9)
+    ap.add_argument("--no-stream-reference", action="store_true", help="skip the torch copy/fill reference")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run 3 plain device copies of this size (counter calibration)")
     args = ap.parse_args()
@@ -334,6 +335,34 @@ def main():
     fluid_nodes = w.nodes - solid_nodes
     r32 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP32, args, fluid_nodes, solid_nodes)
     r16 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP16, args, fluid_nodes, solid_nodes)
+
+    # achievable-bandwidth reference in the same run: torch's device copy and
+    # fill of 1 GiB (read + write, write only), best of five
+    stream_ref = None
+    if not args.no_stream_reference:
+        n = (1 << 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+
+        def best_ms(fn):
+            fn()
+            torch.cuda.synchronize()
+            t = []
+            for _ in range(5):
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s0.record()
+                fn()
+                s1.record()
+                torch.cuda.synchronize()
+                t.append(s0.elapsed_time(s1))
+            return min(t)
+
+        tc, tf = best_ms(lambda: b.copy_(a)), best_ms(lambda: b.fill_(2.0))
+        stream_ref = {"kind": "torch copy_ and fill_ of 1 GiB, best of 5",
+                      "copy_GBps": round(2 * (1 << 30) / (tc * 1e-3) / 1e9, 1),
+                      "fill_GBps": round((1 << 30) / (tf * 1e-3) / 1e9, 1)}
+        del a, b
+        torch.cuda.empty_cache()
 
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -389,6 +418,7 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes": alg_bytes,
             "kernel": "k_step_fused<3,...> (one launch per step)",
+            "stream_reference": stream_ref,
         },
     }
     out["fp16_store"] = {

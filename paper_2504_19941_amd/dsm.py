@@ -67,6 +67,12 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libdsm.so not found at {path}: build it with "
                            "`python -m paper_2504_19941_amd.build` (no fallback exists)")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # the one that owns the device buffers and streams handed to it
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.dsm_required_bytes.argtypes = [ctypes.POINTER(dsm_params)]
