@@ -105,13 +105,33 @@ def cpu_baseline(w, seconds: float):
     steps, total = (more, dt_more) if more else (1, dt)
     C2 = o.fields()["C2"]
     o.close()
+    # the same oracle on one core, over two steps of the same lattice
+    o1 = Oracle(w.dim, w.shape, w.kappa, tau=w.tau, mobility=w.mobility, threads=1)
+    o1.set_solid_field(f32(W.flat(w.C1)))
+    o1.set_liquid(f32(W.flat(w.C2)))
+    t0 = time.perf_counter()
+    o1.step(2)
+    dt1 = time.perf_counter() - t0
+    o1.close()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     report = {
         "value": round(w.nodes * steps / total / 1e6, 4),
         "unit": "MLUPS",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{w.name}: {steps} FP64 oracle steps after 1 untimed, {threads} OpenMP threads, "
-                  f"{total:.1f} s",
+                  f"{total:.1f} s; single core: 2 steps, {dt1:.1f} s",
+        "single_core_MLUPS": round(w.nodes * 2 / dt1 / 1e6, 4),
+        "host_cpus": os.cpu_count(),
+        "cpu_model": model,
     }
     return report, 1 + more, C2
 
@@ -312,8 +332,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU only "
-              "(the single-GPU step; see the sharding design for more)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the benchmark runs the step on one GPU "
+              "(a lattice would shard by slabs with one halo exchange per step; that path is not built)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -419,6 +440,7 @@ def main():
             "algorithmic_bytes": alg_bytes,
             "kernel": "k_step_fused<3,...> (one launch per step)",
             "stream_reference": stream_ref,
+            "frac_of_stream_copy": round(achieved / stream_ref["copy_GBps"], 4) if stream_ref else None,
         },
     }
     out["fp16_store"] = {

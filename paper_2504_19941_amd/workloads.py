@@ -190,6 +190,52 @@ def config_3d_pillars(shape=(256, 256, 192), theta_deg: float = 120.0, seed: int
                     solid_stage=dict(n_steps=5000, beta=1e-3, omega=2e-4), seed=seed)
 
 
+def pillar_field(shape, base: int = 8, width: int = 8, pitch: int = 16, height: int = 32,
+                 jitter: int = 2, seed: int = 3, alpha: float = 1.0) -> np.ndarray:
+    """Analytic diffuse solid of the micropillar array of :func:`pillar_mask`
+    (same seed, same jitter draws): C1 = tanh profile of the signed distance
+    to the union of the base slab and the square pillars (box distances,
+    faces half-way between nodes, positive inside).  Each pillar is evaluated
+    on a window around it; pillars are at least 4 nodes apart."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    Z = np.arange(nz, dtype=np.float64)
+    d = np.broadcast_to(periodic_slab_distance(Z, -0.5, base - 0.5, nz), shape).copy()
+    m = 6  # window margin (the tanh profile is flat beyond a few nodes)
+    zlo, zhi = base - 0.5, base + height - 0.5
+    zw = np.arange(max(0, base - m), min(nz, base + height + m))
+    for px in range(nx // pitch):
+        for py in range(ny // pitch):
+            jx, jy = rng.integers(-jitter, jitter + 1, size=2)
+            x0 = px * pitch + (pitch - width) // 2 + int(jx)
+            y0 = py * pitch + (pitch - width) // 2 + int(jy)
+            xs = np.arange(x0 - m, x0 + width + m)
+            ys = np.arange(y0 - m, y0 + width + m)
+            X, Y, Zc = np.meshgrid(xs.astype(float), ys.astype(float), zw.astype(float), indexing="ij")
+            lo = np.array([x0 - 0.5, y0 - 0.5, zlo])
+            hi = np.array([x0 + width - 0.5, y0 + width - 0.5, zhi])
+            P = np.stack([X, Y, Zc])
+            below, above = lo.reshape(3, 1, 1, 1) - P, P - hi.reshape(3, 1, 1, 1)
+            outside = np.sqrt((np.maximum(np.maximum(below, above), 0.0) ** 2).sum(axis=0))
+            inside = np.minimum(-below, -above).min(axis=0)
+            sd = np.where(outside > 0.0, -outside, inside)
+            win = np.ix_(xs % nx, ys % ny, zw)
+            d[win] = np.maximum(d[win], sd)
+    return tanh_profile(d, alpha)
+
+
+def config_3d_pillars_analytic(shape=(256, 256, 192), theta_deg: float = 120.0, seed: int = 3,
+                               liquid=(44, 104)) -> Workload:
+    """The micropillar workload with the analytic diffuse solid of
+    :func:`pillar_field` in place of the solid stage (parity tests give both
+    sides this same C1)."""
+    w = config_3d_pillars(shape, theta_deg, seed, liquid)
+    w.C1 = pillar_field(shape, seed=seed)
+    w.C2 = w.C2 * (1.0 - w.C1)
+    w.name += "-analytic-C1"
+    return w
+
+
 def sinusoid_mask(shape, amplitude: float, wavelength: float, base: float) -> np.ndarray:
     """2D solid below y_s(x) = base + A sin(2 pi x / lambda)."""
     X, Y = _coords(shape)
