@@ -50,9 +50,10 @@ const char* validate(const dsm_params* p) {
     if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
     if (p->dim == 2 && p->nz != 1) return "nz must be 1 when dim == 2";
     if (p->dim == 3 && p->nz < 4) return "nz must be >= 4 when dim == 3";
-    const double nodes = (double)p->nx * (double)p->ny * (double)p->nz;
-    if (nodes * lattice_q(p->dim) > 4294967295.0) return "lattice has more than 2^32 - 1 populations";
-    if ((double)p->nx * (double)(p->dim == 3 ? p->ny : 1) * lattice_q(p->dim) * 4.0 > 2147483647.0)
+    // population slots, rows padded to the row pitch (at most 63 elements more)
+    const double slots = ((double)p->nx + 64.0) * (double)p->ny * (double)p->nz * lattice_q(p->dim);
+    if (slots > 4294967295.0) return "lattice has more than 2^32 - 1 populations";
+    if (((double)p->nx + 64.0) * (double)(p->dim == 3 ? p->ny : 1) * lattice_q(p->dim) * 4.0 > 2147483647.0)
         return "one lattice plane of populations exceeds 2 GiB";
     for (int k = 0; k < 3; ++k)
         if (!(p->kappa[k] >= 0.0) || !isfinite(p->kappa[k])) return "kappa must be finite and >= 0";
@@ -90,9 +91,10 @@ Layout make_layout(const dsm_params* p) {
         return at;
     };
     const int es = p->storage == DSM_STORAGE_FP16 ? 2 : 4;
-    const size_t fbytes = (size_t)pop_bytes((int)Q, (long long)N, es);
+    const size_t NP = (size_t)row_pitch(p->nx, es) * (N / (size_t)p->nx);  // padded rows
+    const size_t fbytes = (size_t)pop_bytes((int)Q, (long long)NP, es);
     L.off_f[0] = take(fbytes);
-    const size_t gbytes = fbytes + N * sizeof(double);
+    const size_t gbytes = fbytes + NP * sizeof(double);
     L.off_g[0] = take(gbytes);
     L.off_f[1] = take(fbytes);
     L.off_g[1] = take(gbytes);
@@ -176,13 +178,11 @@ int download_field(dsm_sim* s, const float* dev, double* host, size_t count) {
     return DSM_OK;
 }
 
-// Populations: host arrays are [Q][N] (direction-major planes of nodes); the
-// device stores them row-interleaved, (row*Q + i)*X + x with n = x + X*row.
 // Population buffers as the kernels take them.
 Pop PF(const dsm_sim* s, int k) { return Pop{s->d.f[k], s->half}; }
 Pop PG(const dsm_sim* s, int k) { return Pop{s->d.g[k], s->half}; }
-size_t f_bytes(const dsm_sim* s) { return (size_t)pop_bytes(s->Q, s->N, s->es); }
-size_t g_bytes(const dsm_sim* s) { return f_bytes(s) + (size_t)s->N * sizeof(double); }
+size_t f_bytes(const dsm_sim* s) { return (size_t)pop_bytes(s->Q, s->geom.NP, s->es); }
+size_t g_bytes(const dsm_sim* s) { return f_bytes(s) + (size_t)s->geom.NP * sizeof(double); }
 
 // Element copies between the device layout and FP32 host staging (FP16
 // elements hold value * kHalfScale).
@@ -215,35 +215,38 @@ int send_elems(dsm_sim* s, void* dev, size_t count) {
 }
 
 // Populations: host arrays are [Q][N] (direction-major planes of nodes); the
-// device stores them row-interleaved, (row*Q + i)*X + x with n = x + X*row.
+// device stores them row-interleaved with row pitch XP, (row*Q + i)*XP + x
+// with n = x + X*row (pop_index), and the FP64 rest plane with the same pitch.
 // For g the rest population (direction 0) lives in the FP64 rest plane.
 int download_pops(dsm_sim* s, const void* dev, double* host, bool is_g) {
-    const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
-    int rc = fetch_elems(s, dev, Q * N);
+    const size_t X = (size_t)s->geom.X, XP = (size_t)s->geom.XP, N = (size_t)s->N, Q = (size_t)s->Q,
+                 rows = N / X;
+    int rc = fetch_elems(s, dev, Q * rows * XP);
     if (rc) return rc;
     for (size_t r = 0; r < rows; ++r)
         for (size_t i = 0; i < Q; ++i)
-            for (size_t x = 0; x < X; ++x) host[i * N + r * X + x] = (double)s->stage_buf[(r * Q + i) * X + x];
+            for (size_t x = 0; x < X; ++x) host[i * N + r * X + x] = (double)s->stage_buf[(r * Q + i) * XP + x];
     if (is_g) {
-        HIP_TRY(hipMemcpyAsync(host, rest_plane(dev, (int)Q, (long long)N, s->es), N * sizeof(double),
-                               hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipMemcpy2DAsync(host, X * sizeof(double), rest_plane(dev, (int)Q, s->geom.NP, s->es),
+                                 XP * sizeof(double), X * sizeof(double), rows, hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
     return DSM_OK;
 }
 
 int upload_pops_one(dsm_sim* s, const double* host, void* dev, bool is_g) {
-    const size_t X = (size_t)s->geom.X, N = (size_t)s->N, Q = (size_t)s->Q, rows = N / X;
-    s->stage_buf.resize(Q * N);
+    const size_t X = (size_t)s->geom.X, XP = (size_t)s->geom.XP, N = (size_t)s->N, Q = (size_t)s->Q,
+                 rows = N / X;
+    s->stage_buf.assign(Q * rows * XP, 0.f);  // padding stays zero
     for (size_t r = 0; r < rows; ++r)
         for (size_t i = 0; i < Q; ++i)
             for (size_t x = 0; x < X; ++x)
-                s->stage_buf[(r * Q + i) * X + x] = (is_g && i == 0) ? 0.f : (float)host[i * N + r * X + x];
-    int rc = send_elems(s, dev, Q * N);
+                s->stage_buf[(r * Q + i) * XP + x] = (is_g && i == 0) ? 0.f : (float)host[i * N + r * X + x];
+    int rc = send_elems(s, dev, Q * rows * XP);
     if (rc) return rc;
     if (is_g) {
-        HIP_TRY(hipMemcpyAsync(rest_plane(dev, (int)Q, (long long)N, s->es), host, N * sizeof(double),
-                               hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipMemcpy2DAsync(rest_plane(dev, (int)Q, s->geom.NP, s->es), XP * sizeof(double), host,
+                                 X * sizeof(double), X * sizeof(double), rows, hipMemcpyHostToDevice, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
     return DSM_OK;
@@ -360,13 +363,17 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     s->p = *p;
     s->Q = lattice_q(p->dim);
     s->N = (long long)p->nx * p->ny * p->nz;
-    if (p->dim == 2)
-        s->geom = Geom{p->nx, 1, p->ny, s->N};
-    else
-        s->geom = Geom{p->nx, p->ny, p->nz, s->N};
     s->stream = (hipStream_t)stream;
     s->half = p->storage == DSM_STORAGE_FP16 ? 1 : 0;
     s->es = s->half ? 2 : 4;
+    {
+        const int XP = row_pitch(p->nx, s->es);
+        const long long NP = (long long)XP * (s->N / p->nx);
+        if (p->dim == 2)
+            s->geom = Geom{p->nx, 1, p->ny, s->N, XP, NP};
+        else
+            s->geom = Geom{p->nx, p->ny, p->nz, s->N, XP, NP};
+    }
     char* base = (char*)dev_buf;
     for (int k = 0; k < 2; ++k) {
         s->d.f[k] = base + L.off_f[k];
@@ -392,7 +399,9 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     s->tau_s = 1.0;
     s->taug_s = 1.0;
     s->tile_variant = p->dim == 3 ? 2 : 0;
-    s->tile_planes = 16;
+    // FP16 3D tiles run two per CU (see the tile kernels' occupancy), so
+    // shorter marches keep twice as many tiles in flight
+    s->tile_planes = p->dim == 3 && s->half ? 8 : 16;
     auto cleanup = [&](int rc) {
         delete s;
         return rc;
@@ -666,7 +675,7 @@ int dsm_get_state(dsm_sim* s, void* host, size_t bytes) {
     StateHeader h;
     memset(&h, 0, sizeof(h));
     h.magic = kStateMagic;
-    h.version = 2;
+    h.version = 3;  // 3: population and rest-plane rows padded to the row pitch
     h.dim = s->p.dim;
     h.nx = s->p.nx;
     h.ny = s->p.ny;
@@ -699,7 +708,7 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
     if (bytes != dsm_state_bytes(s)) return fail(DSM_EINVAL, "state size mismatch");
     StateHeader h;
     memcpy(&h, host, sizeof(h));
-    if (h.magic != kStateMagic || h.version != 2) return fail(DSM_EINVAL, "not a dsm state image (or an older format)");
+    if (h.magic != kStateMagic || h.version != 3) return fail(DSM_EINVAL, "not a dsm state image (or an older format)");
     if (h.dim != s->p.dim || h.nx != s->p.nx || h.ny != s->p.ny || h.nz != s->p.nz)
         return fail(DSM_EINVAL, "state image is for another lattice");
     if (h.stage != 1 && h.stage != 2) return fail(DSM_EINVAL, "state image has no live stage");

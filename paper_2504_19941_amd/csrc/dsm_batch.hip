@@ -205,6 +205,8 @@ int refresh(dsm_batch* b) {
         d.geom.Y = s->geom.Y;
         d.geom.Z = s->geom.Z;
         d.geom.N = s->geom.N;
+        d.geom.XP = s->geom.XP;
+        d.geom.NP = s->geom.NP;
         d.phys = sim_phys(s, 2);
         d.f[0] = s->d.f[s->cur];
         d.f[1] = s->d.f[1 - s->cur];

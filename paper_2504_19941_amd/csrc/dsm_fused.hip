@@ -26,9 +26,11 @@
 // warm-up plane on each side of the march.
 //
 // Addressing.  Populations are stored row-interleaved: the Q values of the X
-// nodes of one row are contiguous, direction-major (dsm_lattice.h).  A wave's
-// row is uniform, so the 9 source rows of a pull are scalar base addresses
-// and the lanes only add their (wrapped) x - 1, x, x + 1.
+// nodes of one row are contiguous, direction-major, each direction row padded
+// to a whole number of 128-byte lines (dsm_lattice.h).  A wave's row is
+// uniform, so the 9 source rows of a pull are scalar base addresses and the
+// lanes only add their (wrapped) x - 1, x, x + 1; the own-column stores fill
+// whole lines.
 //
 // Mass.  BGK conserves sum_i g_i at each node and streaming only moves
 // values, so the liquid mass is exact up to rounding.  The rest population
@@ -90,13 +92,6 @@ struct Tile {
 };
 
 
-// Occupancy request for the fused kernel (none by default).
-#ifdef DSM_FUSED_WPE
-#define DSM_WAVES_PER_EU __attribute__((amdgpu_waves_per_eu(DSM_FUSED_WPE, 8)))
-#else
-#define DSM_WAVES_PER_EU
-#endif
-
 // Buffer resources.  Every plane of populations gets a descriptor (base =
 // start of the plane, range = one plane), so the hot loads and stores address
 // with a scalar offset (row and direction, uniform per wave) plus a 32-bit
@@ -114,12 +109,30 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, l
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)plane_bytes, kRsrcWord3);
 }
 
-// Population element types: loads return the value, stores write it
-// (non-temporal) and return the value as stored, after rounding.
+// Population element types: loads return the value (raw: the stored bits,
+// value: their meaning), stores write it (non-temporal) and return the value
+// as stored, after rounding.
+//
+// Occupancy.  The 3D tile holds the pulled g of its lead plane for one
+// iteration, until that plane's collision; in registers that brings it to
+// about 150 VGPRs, 3 waves per SIMD, one 8-wave tile per CU.  FP16 elements
+// are held instead as their raw bits in a two-slot LDS buffer of per-thread
+// cells (exact, 2 bytes each), and the FP16 tile kernels request 4 waves per
+// SIMD, so two tiles share a CU: the FP16 step moves half the bytes per
+// memory instruction and is latency-bound at one tile per CU.  The FP32 step
+// is bound by the memory system, gains nothing from a second tile, and keeps
+// its registers (min_waves 1: no request).
 struct F32 {
+    using Raw = unsigned;
     static constexpr unsigned bytes = 4;
+    static constexpr int min_waves = 1;
+    static constexpr bool lds_hold = false;
+    static __device__ __forceinline__ Raw load_raw(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+    }
+    static __device__ __forceinline__ float value(Raw b) { return __uint_as_float(b); }
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+        return value(load_raw(r, voff, soff));
     }
     static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNonTemporal);
@@ -127,10 +140,18 @@ struct F32 {
     }
 };
 struct F16 {  // FP16 holding value * kHalfScale
+    using Raw = unsigned short;
     static constexpr unsigned bytes = 2;
-    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    static constexpr int min_waves = 4;
+    static constexpr bool lds_hold = true;
+    static __device__ __forceinline__ Raw load_raw(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+    }
+    static __device__ __forceinline__ float value(Raw h) {
         return __half2float(__ushort_as_half(h)) * (1.f / kHalfScale);
+    }
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+        return value(load_raw(r, voff, soff));
     }
     static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
         const __half h = __float2half(v * kHalfScale);
@@ -153,9 +174,12 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
     constexpr int CRX = T::CRX, CR = T::CR, HY = T::HY;
     __shared__ float s_c[4][CR];                                    // C of planes l-3..l (ring)
     __shared__ float s_c1[STAGE == 2 ? 4 : 1][STAGE == 2 ? CR : 1];  // frozen C1, same ring
+    // held lead-plane g of the own column (FP16: raw bits, slot j & 1)
+    constexpr int HOLD = E::lds_hold ? T::NT : 1;
+    __shared__ typename E::Raw s_gh[E::lds_hold ? 2 : 1][E::lds_hold ? Q - 1 : 1][HOLD];
 
-    const int X = g.X, Y = g.Y, Z = g.Z;
-    const int QX = Q * X;                               // elements per row of populations
+    const int X = g.X, Y = g.Y, Z = g.Z, XP = g.XP;
+    const int QX = Q * XP;                              // elements per row of populations
     const long long PL = (long long)QX * Y * E::bytes;  // bytes per plane of populations
     constexpr unsigned ES = E::bytes;
     const int zlen = min(TZ, Z - z0);
@@ -192,8 +216,8 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
 
     const float fpref3 = 3.f * ph.fpref;
     const float k13 = ph.k1 + ph.k3;
-    const double* __restrict__ g0src = rest_plane(gsrc, Q, g.N, ES);
-    double* __restrict__ g0dst = rest_plane(gdst, Q, g.N, ES);
+    const double* __restrict__ g0src = rest_plane(gsrc, Q, g.NP, ES);
+    double* __restrict__ g0dst = rest_plane(gdst, Q, g.NP, ES);
     float gA[Q], gB[Q];
 
     auto iteration = [&](int j, float (&gload)[Q], float (&gcoll)[Q], double& cload, double& ccoll) {
@@ -213,15 +237,21 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
         // of the node, and C = g_0 + sum_{i>0} g_i in FP64
         {
             const long long node = xv[1] + X * ((long long)yv[1] + (long long)Y * lz);
-            const double r0 = g0src[node];
+            const double r0 = g0src[xv[1] + XP * ((long long)yv[1] + (long long)Y * lz)];
+            typename E::Raw raw[Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                gload[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * X));
+                raw[i] = E::load_raw(gl[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * XP));
+                gload[i] = E::value(raw[i]);
             }
             double acc = 0.0;
 #pragma unroll
             for (int i = 1; i < Q; ++i) acc += (double)gload[i];
+            if (E::lds_hold) {
+#pragma unroll
+                for (int i = 1; i < Q; ++i) s_gh[j & 1][i - 1][t] = raw[i];
+            }
             cload = r0 + acc;
             s_c[sl][rint] = (float)cload;
             if (STAGE == 2) s_c1[sl][rint] = c1g[node];
@@ -229,12 +259,12 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
         // lead plane, halo columns (same summation order as the own column)
         if (row_halo) {
             const long long node = xv[1] + X * ((long long)hyw + (long long)Y * lz);
-            const double r0 = g0src[node];
+            const double r0 = g0src[xv[1] + XP * ((long long)hyw + (long long)Y * lz)];
             float h[Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                h[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(hyv[sy] * QX + i * X));
+                h[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(hyv[sy] * QX + i * XP));
             }
             double acc = 0.0;
 #pragma unroll
@@ -243,12 +273,12 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
             if (STAGE == 2) s_c1[sl][hreg] = c1g[node];
         } else if (side) {
             const long long node = sxw + X * ((long long)syw + (long long)Y * lz);
-            const double r0 = g0src[node];
+            const double r0 = g0src[sxw + XP * ((long long)syw + (long long)Y * lz)];
             float h[Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                h[i] = E::load(gl[sz], ES * (unsigned)(syv[sy] * QX + i * X + sxv[sx]), 0u);
+                h[i] = E::load(gl[sz], ES * (unsigned)(syv[sy] * QX + i * XP + sxv[sx]), 0u);
             }
             double acc = 0.0;
 #pragma unroll
@@ -266,7 +296,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                f[i] = E::load(fc[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * X));
+                f[i] = E::load(fc[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * XP));
             }
         }
         __syncthreads();
@@ -384,7 +414,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
                     feq = L::w[i] * (pt + si);
                     fi = fp3 * L::w[i] * cF;
                 }
-                E::store(fo, xb[1], own_off + ES * (unsigned)(i * X), f[i] - (f[i] - feq) * itau + fi);
+                E::store(fo, xb[1], own_off + ES * (unsigned)(i * XP), f[i] - (f[i] - feq) * itau + fi);
             }
         }
         const __amdgpu_buffer_rsrc_t go = plane_rsrc(gdst, PL, c);
@@ -395,10 +425,11 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
         for (int i = 1; i < Q; ++i) {
             const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
             const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
-            const float gs = gcoll[i] - (gcoll[i] - geq) * ph.inv_taug;
-            moved += (double)E::store(go, xb[1], own_off + ES * (unsigned)(i * X), gs);
+            const float gc = E::lds_hold ? E::value(s_gh[(j + 1) & 1][i - 1][t]) : gcoll[i];
+            const float gs = gc - (gc - geq) * ph.inv_taug;
+            moved += (double)E::store(go, xb[1], own_off + ES * (unsigned)(i * XP), gs);
         }
-        __builtin_nontemporal_store(ccoll - moved, g0dst + (xv[1] + X * ((long long)yv[1] + (long long)Y * c)));
+        __builtin_nontemporal_store(ccoll - moved, g0dst + (xv[1] + XP * ((long long)yv[1] + (long long)Y * c)));
         if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
     };
 
@@ -411,7 +442,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
 }
 
 template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
-__global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
+__global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per_eu(E::min_waves)))
     k_step_fused(Geom g, Phys ph, const void* __restrict__ fsrc, const void* __restrict__ gsrc,
                  void* __restrict__ fdst, void* __restrict__ gdst, const float* __restrict__ c1g,
                  const uint8_t* __restrict__ mask, int* __restrict__ flag, int TZ, int ntx, int nty) {
@@ -436,7 +467,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) DSM_WAVES_PER_EU
 // geometry, parameters and buffers come from a descriptor table, with the
 // two buffer pairs exchanged by the step parity.
 template <int D, int TXW, int TY, bool RHO, typename E>
-__global__ void __launch_bounds__(64 * TXW * TY)
+__global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per_eu(E::min_waves)))
     k_step_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems,
                  int* __restrict__ counter, int parity, int TZ) {
     __shared__ int s_item;

@@ -187,7 +187,7 @@ __global__ void k_moment(Geom g, Pop gsrc, float* __restrict__ phi, int pull) {
         long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
         acc += (double)gsrc.ld(pop_index(g, L::Q, i, src));
     }
-    phi[n] = (float)(gsrc.rest(L::Q, g.N)[n] + acc);
+    phi[n] = (float)(gsrc.rest(L::Q, g.NP)[rest_index(g, n)] + acc);
 }
 
 // chemical potential of the fluid stage (mu = dPsi/dC2) or of the solid stage
@@ -327,7 +327,7 @@ __global__ void k_collide(Geom g, Phys ph, Pop fsrc, Pop gsrc,
         gi[i] = gsrc.ld(pop_index(g, L::Q, i, src));
         C64 += (double)gi[i];
     }
-    C64 += gsrc.rest(Q, N)[n];
+    C64 += gsrc.rest(Q, g.NP)[rest_index(g, n)];
     // rest population (FP64) = C - sum of the moving post-collision populations
     double moved = 0.0;
 #pragma unroll
@@ -337,7 +337,7 @@ __global__ void k_collide(Geom g, Phys ph, Pop fsrc, Pop gsrc,
         float gs = gi[i] - (gi[i] - geq) * ph.inv_taug;
         moved += (double)gdst.st(pop_index(g, L::Q, i, n), gs);
     }
-    gdst.rest(Q, N)[n] = C64 - moved;
+    gdst.rest(Q, g.NP)[rest_index(g, n)] = C64 - moved;
     if (!isfinite(C) || !isfinite(uu)) flag[0] = 1;
 }
 
@@ -357,7 +357,7 @@ __global__ void k_init_populations(Geom g, const float* __restrict__ phi, const 
         fdst.st(pop_index(g, L::Q, i, n), 0.f);
     }
     gdst.st(pop_index(g, L::Q, 0, n), 0.f);  // unused slot: the rest population is FP64
-    gdst.rest(L::Q, g.N)[n] = (double)C - moved;
+    gdst.rest(L::Q, g.NP)[rest_index(g, n)] = (double)C - moved;
     fdst.st(pop_index(g, L::Q, 0, n), 0.f);
 }
 
@@ -374,7 +374,7 @@ __global__ void k_pull_state(Geom g, Phys ph, Pop fsrc, Pop gsrc,
 #pragma unroll
     for (int i = 1; i < Q; ++i) gdst.st(pop_index(g, L::Q, i, n), gsrc.ld(pop_index(g, L::Q, i, shifted<D>(g, x, y, z, i, -1))));
     gdst.st(pop_index(g, L::Q, 0, n), 0.f);
-    gdst.rest(Q, g.N)[n] = gsrc.rest(Q, g.N)[n];
+    gdst.rest(Q, g.NP)[rest_index(g, n)] = gsrc.rest(Q, g.NP)[rest_index(g, n)];
     const bool solid = ph.stage == 2 && c1[n] > 0.5f;
     float f[Q];
     if (solid) {
@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce(Geom g, Phys ph, const float*
         double C3 = 1.0 - C1 - C2;
         // masses: the evolving component summed in FP64 from the stored
         // populations themselves, so that drift measures the stored state
-        double cm = gsrc.rest(L::Q, N)[n];
+        double cm = gsrc.rest(L::Q, g.NP)[rest_index(g, n)];
         for (int i = 1; i < L::Q; ++i) {
             const long long src = pull ? shifted<D>(g, x, y, z, i, -1) : n;
             cm += (double)gsrc.ld(pop_index(g, L::Q, i, src));

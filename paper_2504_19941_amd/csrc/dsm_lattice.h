@@ -45,11 +45,25 @@ struct Lattice<3> {
 
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
-// Storage geometry: X fastest, Z slowest.  For dim 2, Y == 1.
+// Storage geometry: X fastest, Z slowest.  For dim 2, Y == 1.  Node-indexed
+// arrays (C1, the mask, the split kernels' fields) are dense, n = x + X*row;
+// population rows and the FP64 rest plane use the row pitch XP >= X, a whole
+// number of 128-byte lines (see pop_index).
 struct Geom {
     int X, Y, Z;
-    long long N;  // X*Y*Z
+    long long N;   // X*Y*Z
+    int XP;        // row pitch of the population and rest-plane layouts, in elements
+    long long NP;  // XP*Y*Z
 };
+
+// Row pitch for populations of elem_bytes bytes: X rounded up to a multiple
+// of 128 bytes, so every direction row of every lattice row starts on a line
+// (a wave's 64 consecutive elements then fill whole lines, which the HBM
+// writes without merging partial lines).
+__host__ __device__ __forceinline__ int row_pitch(int X, int elem_bytes) {
+    const int k = 128 / elem_bytes;
+    return (X + k - 1) / k * k;
+}
 
 // Physical and scheme parameters in the form the kernels use them.
 struct Phys {
@@ -85,9 +99,11 @@ __device__ __forceinline__ long long node_index(const Geom& g, int x, int y, int
 
 // Population layout in HBM, "row-interleaved": the Q populations of the X
 // nodes of one lattice row (fixed stored y and z) are contiguous and
-// direction-major, so population i of node n = x + X*row lives at
-// (row*Q + i)*X + x.  A wave reading one direction of one row segment then
-// touches one contiguous run, and a node's Q values sit within Q*X floats.
+// direction-major, each direction row padded to the pitch XP, so population
+// i of node n = x + X*row lives at (row*Q + i)*XP + x.  A wave reading one
+// direction of one row segment then touches one contiguous, line-aligned
+// run, and a node's Q values sit within Q*XP elements.  Padding is never
+// read or written by the kernels.
 // Population storage.  FP32 (4-byte) or FP16 (2-byte) elements; FP16 holds
 // value * kHalfScale, since the populations of this scheme are deviations
 // from the rest state (f is zero at rest, and the moving g are w_i mu plus
@@ -95,9 +111,10 @@ __device__ __forceinline__ long long node_index(const Geom& g, int x, int y, int
 // in the subnormal range of FP16.
 constexpr float kHalfScale = 4096.f;
 
-// The g populations of one buffer: the Q*N slots of the population layout,
+// The g populations of one buffer: the Q*NP slots of the population layout,
 // of which the moving directions i > 0 are used, followed (256-byte aligned)
-// by the rest population g_0 of every node in FP64, node order.  The rest
+// by the rest population g_0 of every node in FP64, rows of pitch XP
+// (rest_index).  The rest
 // population carries nearly all of C, so storing it in FP64 keeps the liquid
 // mass from drifting by rounding at the scale of C (the moving populations
 // are small and their rounding is negligible).
@@ -135,7 +152,13 @@ struct Pop {
 
 __host__ __device__ __forceinline__ long long pop_index(const Geom& g, int Q, int i, long long n) {
     const long long row = n / g.X;
-    return (row * Q + i) * g.X + (n - row * g.X);
+    return (row * Q + i) * g.XP + (n - row * g.X);
+}
+
+// Element of node n in the FP64 rest plane.
+__host__ __device__ __forceinline__ long long rest_index(const Geom& g, long long n) {
+    const long long row = n / g.X;
+    return row * g.XP + (n - row * g.X);
 }
 
 }  // namespace dsm

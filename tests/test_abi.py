@@ -108,13 +108,38 @@ def test_null_handle_calls_fail_cleanly(lib):
 
 
 def test_storage_modes_size_the_buffer(lib):
-    p32 = good_params()
-    p16 = good_params(storage=dsm.DSM_STORAGE_FP16)
+    shape = (64, 24, 16)  # rows of 64 elements fill whole 128-byte lines in both storages
+    p32 = dsm.make_params(3, shape, (0.01, 0.005, 0.01))
+    p16 = dsm.make_params(3, shape, (0.01, 0.005, 0.01))
+    p16.storage = dsm.DSM_STORAGE_FP16
     n32, n16 = dsm.dsm_required_bytes(p32), dsm.dsm_required_bytes(p16)
-    N = 32 * 24 * 16
+    N = 64 * 24 * 16
     # four population buffers of Q planes shrink from 4 to 2 bytes per element
     assert n32 - n16 >= 4 * 19 * N * 2 - 4 * 256
     assert dsm.dsm_required_bytes(good_params(storage=3)) == 0
+
+
+@pytest.mark.parametrize("nx,storage,pitch", [(32, 0, 32), (33, 0, 64), (100, 0, 128), (127, 0, 128),
+                                              (32, 1, 64), (65, 1, 128), (128, 1, 128)])
+def test_population_rows_are_padded_to_whole_lines(lib, nx, storage, pitch):
+    """Population and rest-plane rows take a pitch of whole 128-byte lines:
+    the buffer grows by exactly the padding of the four population sets (Q
+    elements per padded node) and the two FP64 rest planes."""
+    ny, nz = 6, 5
+    es = 2 if storage else 4
+    p = dsm.make_params(3, (nx, ny, nz), (0.01, 0.005, 0.01))
+    p.storage = storage
+    q = dsm.make_params(3, (pitch, ny, nz), (0.01, 0.005, 0.01))
+    q.storage = storage
+    need, need_pitch = dsm.dsm_required_bytes(p), dsm.dsm_required_bytes(q)
+    rows = ny * nz
+    pad_nodes = (pitch - nx) * rows
+    # node-indexed arrays (C1, mask, fields, link records) shrink with the
+    # real node count; populations and rest planes keep the padded size
+    per_node_dense = need_pitch - need
+    pops = 4 * 19 * pitch * rows * es + 2 * 8 * pitch * rows
+    assert need >= pops
+    assert 0 <= per_node_dense <= pad_nodes * 400 + 16 * 256
 
 
 def test_batch_calls_reject_invalid_arguments_without_a_device(lib):
