@@ -256,10 +256,10 @@ int dsm_batch_get_schedule(const dsm_batch* b, int dim, dsm_batch_schedule* sche
 
 /* Autotuner: for each lattice type present, scores every tile variant with
  * each of the plane counts 8, 16, 32, 64 and 128 by a model of the batched
- * step over the members' actual shapes (waves per work item, the two fill
- * planes of every item, the resident waves the dynamic queue keeps busy, the
- * tail left by the longest item, and a per-variant cost of one wave-plane
- * measured on MI355X), and installs the best.
+ * step over the members' actual shapes (waves per work item, the resident
+ * waves the dynamic queue keeps busy, the tail left by the longest item, and
+ * a per-variant cost of one wave-plane fitted to step times measured on
+ * MI355X), and installs the best.
  * No device work is issued, so the members' states and step counts are
  * unchanged.  reps must be 0 (timed tuning is not offered).  cost (may be
  * NULL) receives the modelled cost of the chosen schedule of each type
