@@ -23,7 +23,10 @@
 // of the iteration before or of the same iteration, so one barrier per plane
 // suffices.  Halo columns are the only recomputation (their loads hit in L2,
 // where the neighbouring tile of the same XCD reads the same lines), plus one
-// warm-up plane on each side of the march.
+// warm-up plane on each side of the march.  Two forms of the tile share this
+// scheme: fused_tile (FP16 elements, held g in LDS) issues each plane's loads
+// in its own phase 1; fused_tile_pipe (FP32) issues them one plane ahead,
+// before the previous plane's stores (see there).
 //
 // Addressing.  Populations are stored row-interleaved: the Q values of the X
 // nodes of one row are contiguous, direction-major, each direction row padded
@@ -441,6 +444,355 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Pipelined tile (register-held elements).  The same march and arithmetic as
+// fused_tile, with the memory operations reordered: the loads of plane j + 1
+// (its pulled g, rest population and C1, and the f of the next collision
+// plane) are issued right after the barrier of plane j, before plane j's
+// collision and stores.  A lane's vector-memory operations complete in
+// order, loads and stores alike, so a wait for a load also waits for every
+// store issued before it; issued ahead of the stores, the next plane's loads
+// never wait for them, and each plane's loads have a whole collision to land.
+// Every memory operation of the steady-state loop is issued unconditionally
+// (lanes outside the lattice and, for f, solid nodes address past the plane:
+// their loads return 0 and their stores are dropped; the last plane's
+// prefetch uses an empty descriptor), so the compiler's wait counts are exact.
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+constexpr unsigned kOOB = 0x80000000u;  // lane offset past every plane
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_v(const void* base, long long plane_bytes, int z,
+                                                              bool valid) {
+    const unsigned long long a = (unsigned long long)base + (unsigned long long)(plane_bytes * z);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    void* p = reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, valid ? (int)plane_bytes : 0, kRsrcWord3);
+}
+
+template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
+__device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, const void* __restrict__ fsrc,
+                                                const void* __restrict__ gsrc, void* __restrict__ fdst,
+                                                void* __restrict__ gdst, const float* __restrict__ c1g,
+                                                const uint8_t* __restrict__ mask, int* __restrict__ flag, int x0,
+                                                int y0, int z0, int TZ) {
+    using T = Tile<D, TXW, TY>;
+    using L = Lattice<D>;
+    constexpr int Q = L::Q;
+    constexpr int CRX = T::CRX, CR = T::CR, HY = T::HY;
+    __shared__ float s_c[4][CR];                                    // C of planes l-3..l (ring)
+    __shared__ float s_c1[STAGE == 2 ? 4 : 1][STAGE == 2 ? CR : 1];  // frozen C1, same ring
+
+    const int X = g.X, Y = g.Y, Z = g.Z, XP = g.XP;
+    const int QX = Q * XP;                              // elements per row of populations
+    const long long PL = (long long)QX * Y * E::bytes;  // bytes per plane of populations
+    const long long RPL = (long long)XP * Y * 8;        // bytes per plane of the rest plane
+    constexpr unsigned ES = E::bytes;
+    const int zlen = min(TZ, Z - z0);
+
+    const int t = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index (uniform)
+    const int lane = t & 63;
+    const int xseg = wv % TXW, yrow = wv / TXW;
+    const int x = x0 + xseg * 64 + lane;
+    const int y = y0 + yrow;  // uniform
+    const bool active = (x < X) && (y < Y);
+    const int rint = (1 + xseg * 64 + lane) + CRX * (HY + yrow);  // own region index
+
+    const int xv[3] = {pmod(x - 1, X), pmod(x, X), pmod(x + 1, X)};  // x-1, x, x+1
+    const unsigned xb[3] = {ES * xv[0], ES * xv[1], ES * xv[2]};        // as byte offsets
+    const int yw = pmod(y, Y);
+    const int yv[3] = {yw == 0 ? Y - 1 : yw - 1, yw, yw + 1 == Y ? 0 : yw + 1};
+
+    const bool row_halo = wv < T::NROWH;  // uniform
+    const int hbot = HY ? (wv / TXW) : 0;  // 0: row above the tile, 1: row below
+    const int hyw = pmod(hbot ? y0 + TY : y0 - 1, Y);
+    const int hyv[3] = {hyw == 0 ? Y - 1 : hyw - 1, hyw, hyw + 1 == Y ? 0 : hyw + 1};
+    const int hreg = (1 + xseg * 64 + lane) + CRX * (hbot ? T::CRY - 1 : 0);
+    const bool side = wv == T::SIDE && lane < T::NSIDE;
+    int srx = 0, sry = 0;
+    if (side) T::side_pos(lane, srx, sry);
+    const int sreg = srx + CRX * sry;
+    const int sxw = pmod(x0 - 1 + srx, X), syw = pmod(y0 - HY + sry, Y);
+    const int sxv[3] = {sxw == 0 ? X - 1 : sxw - 1, sxw, sxw + 1 == X ? 0 : sxw + 1};
+    const int syv[3] = {syw == 0 ? Y - 1 : syw - 1, syw, syw + 1 == Y ? 0 : syw + 1};
+
+    const float fpref3 = 3.f * ph.fpref;
+    const float k13 = ph.k1 + ph.k3;
+    const double* __restrict__ g0src = rest_plane(gsrc, Q, g.NP, ES);
+    double* __restrict__ g0dst = rest_plane(gdst, Q, g.NP, ES);
+    const unsigned own_off = ES * (unsigned)(yv[1] * QX);
+    const unsigned g0_off = active ? 8u * (unsigned)(xv[1] + XP * yv[1]) : kOOB;
+
+    float gF[Q], hF[Q], fF[Q];  // issued for the next plane
+    float gN[Q], gC[Q], fN[Q];  // lead plane's g, collision plane's g and f
+    double r0F = 0.0, hr0F = 0.0, cN = 0.0, cC = 0.0;
+    float c1F = 0.f, hc1F = 0.f;
+    uint8_t mF = 0, mN = 0;
+    bool bad = false;
+    const int J = zlen + 2;
+
+    // loads of the lead plane of iteration jn: own column and halo column
+    auto issue_g = [&](int jn, bool valid) {
+        const int lz = pmod(z0 - 1 + jn, Z);
+        const int zl[3] = {lz == 0 ? Z - 1 : lz - 1, lz, lz + 1 == Z ? 0 : lz + 1};
+        const __amdgpu_buffer_rsrc_t gl[3] = {plane_rsrc_v(gsrc, PL, zl[0], valid),
+                                              plane_rsrc_v(gsrc, PL, zl[1], valid),
+                                              plane_rsrc_v(gsrc, PL, zl[2], valid)};
+        r0F = g0src[xv[1] + XP * ((long long)yv[1] + (long long)Y * lz)];
+        if (STAGE == 2) c1F = c1g[xv[1] + X * ((long long)yv[1] + (long long)Y * lz)];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+            gF[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * XP));
+        }
+        if (row_halo) {
+            hr0F = g0src[xv[1] + XP * ((long long)hyw + (long long)Y * lz)];
+            if (STAGE == 2) hc1F = c1g[xv[1] + X * ((long long)hyw + (long long)Y * lz)];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+                hF[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(hyv[sy] * QX + i * XP));
+            }
+        } else if (side) {
+            hr0F = g0src[sxw + XP * ((long long)syw + (long long)Y * lz)];
+            if (STAGE == 2) hc1F = c1g[sxw + X * ((long long)syw + (long long)Y * lz)];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+                hF[i] = E::load(gl[sz], ES * (unsigned)(syv[sy] * QX + i * XP + sxv[sx]), 0u);
+            }
+        }
+    };
+    // f of the collision plane of iteration jn (the lead plane of jn - 1);
+    // need: the lane is a fluid node of the lattice
+    auto issue_f = [&](int jn, bool valid, bool need) {
+        const int cz = pmod(z0 - 2 + jn, Z);
+        const int zc[3] = {cz == 0 ? Z - 1 : cz - 1, cz, cz + 1 == Z ? 0 : cz + 1};
+        const __amdgpu_buffer_rsrc_t fc[3] = {plane_rsrc_v(fsrc, PL, zc[0], valid),
+                                              plane_rsrc_v(fsrc, PL, zc[1], valid),
+                                              plane_rsrc_v(fsrc, PL, zc[2], valid)};
+        const unsigned xf[3] = {need ? xb[0] : kOOB, need ? xb[1] : kOOB, need ? xb[2] : kOOB};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
+            fF[i] = E::load(fc[sz], xf[sx], ES * (unsigned)(yv[sy] * QX + i * XP));
+        }
+        if (STAGE == 1) mF = mask[xv[1] + X * ((long long)yv[1] + (long long)Y * cz)];
+    };
+    // phase 1: C = g_0 + sum_{i>0} g_i in FP64 of the lead plane (own column,
+    // then the halo column, same summation order) into ring slot j & 3
+    auto consume_lead = [&](int j) {
+        const int sl = j & 3;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) gN[i] = gF[i];
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) acc += (double)gN[i];
+        cN = r0F + acc;
+        s_c[sl][rint] = (float)cN;
+        if (STAGE == 2) s_c1[sl][rint] = c1F;
+        if (row_halo || side) {
+            double a = 0.0;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) a += (double)hF[i];
+            const int hr = row_halo ? hreg : sreg;
+            s_c[sl][hr] = (float)(hr0F + a);
+            if (STAGE == 2) s_c1[sl][hr] = hc1F;
+        }
+    };
+    auto lead_solid = [&](int j) { return STAGE == 2 && s_c1[j & 3][rint] > 0.5f; };
+
+    // warm-up: the two planes before the first collision
+    issue_g(0, true);
+    consume_lead(0);
+    __syncthreads();
+    issue_g(1, true);
+    cC = cN;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) gC[i] = gN[i];
+    consume_lead(1);
+    __syncthreads();
+    issue_g(2, true);
+    issue_f(2, true, active && !lead_solid(1));
+    {
+        // the stores of a collision, to an empty descriptor (all dropped): the
+        // loop is entered with the same memory operations in flight as when
+        // it goes round, so the waits inside it need not be conservative
+        const __amdgpu_buffer_rsrc_t none = plane_rsrc_v(fdst, PL, 0, false);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) E::store(none, kOOB, own_off + ES * (unsigned)(i * XP), 0.f);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) E::store(none, kOOB, own_off + ES * (unsigned)(i * XP), 0.f);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, 0.0), none, (int)kOOB, 0, kNonTemporal);
+    }
+    cC = cN;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) gC[i] = gN[i];
+
+    for (int j = 2; j < J; ++j) {
+        const int c = z0 - 2 + j;  // collision plane, inside [0, Z)
+        consume_lead(j);
+        __syncthreads();
+        const int sm_ = (j + 2) & 3, s0 = (j + 3) & 3, sp = j & 3;  // planes c-1, c, c+1
+        const bool solid = STAGE == 2 && s_c1[s0][rint] > 0.5f;
+        // f of plane c (issued one plane ago): its moments first, so that the
+        // wait for it comes before the next plane's loads are issued
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fN[i] = fF[i];
+        if (STAGE == 1) mN = mF;
+        float pt = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+        if (!solid) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                pt += fN[i];
+                mx += L::cx[i] * fN[i];
+                my += L::cy[i] * fN[i];
+                mz += L::cz[i] * fN[i];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const bool more = j + 1 < J;  // uniform
+        issue_g(j + 1, more);
+        issue_f(j + 1, more, active && !lead_solid(j));
+        __builtin_amdgcn_sched_barrier(0);
+
+        // ---- collide plane c ------------------------------------------------
+        const float C = s_c[s0][rint];
+        float lc = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);  // plane of x + c_i
+            const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);  // plane of x - c_i
+            const int o = L::cx[i] + CRX * L::cy[i];
+            const float a = s_c[spl][rint + o], bm = s_c[smi][rint - o];
+            lc += L::w[i] * ((a - C) + (bm - C));
+            const float d = a - bm;
+            gx += L::w[i] * L::cx[i] * d;
+            gy += L::w[i] * L::cy[i] * d;
+            gz += L::w[i] * L::cz[i] * d;
+        }
+        lc *= 6.f;
+        float mu, C1 = 0.f;
+        float rho = 1.f, grx = 0.f, gry = 0.f, grz = 0.f;
+        if (STAGE == 2) {
+            C1 = s_c1[s0][rint];
+            float l1 = 0.f;
+#pragma unroll
+            for (int i = 1; i < Q; i += 2) {
+                const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);
+                const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);
+                const int o = L::cx[i] + CRX * L::cy[i];
+                const float a1 = s_c1[spl][rint + o], b1 = s_c1[smi][rint - o];
+                l1 += L::w[i] * ((a1 - C1) + (b1 - C1));
+                if (RHO) {
+                    const float d = local_density(ph, s_c[spl][rint + o], a1) -
+                                    local_density(ph, s_c[smi][rint - o], b1);
+                    grx += L::w[i] * L::cx[i] * d;
+                    gry += L::w[i] * L::cy[i] * d;
+                    grz += L::w[i] * L::cz[i] * d;
+                }
+            }
+            l1 *= 6.f;
+            if (RHO) {
+                rho = local_density(ph, C, C1);
+                grx *= 3.f;
+                gry *= 3.f;
+                grz *= 3.f;
+            }
+            const float S = C1 + C;
+            mu = ph.k2 * C * (1.f - C) * (1.f - 2.f * C) + ph.k3 * S * (1.f - S) * (1.f - 2.f * S) -
+                 ph.a2 * ph.k2 * lc - ph.a2 * ph.k3 * (l1 + lc);
+        } else {
+            mu = k13 * C * (1.f - C) * (1.f - 2.f * C);
+            const bool inS = mN != 0;
+            if ((C < 0.5f && inS) || (C > 0.5f && !inS)) mu += 2.f * ph.beta * (C - 0.5f);
+            mu -= ph.a2 * k13 * lc;
+            if (C < 0.f) mu += 2.f * ph.omega * C;
+            if (C > 1.f) mu -= 2.f * ph.omega * (1.f - C);
+        }
+        float ux = 0.f, uy = 0.f, uz = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
+        if (!solid) {
+            Fx = mu * 3.f * gx;
+            Fy = mu * 3.f * gy;
+            Fz = mu * 3.f * gz;
+            if (STAGE == 2) {
+                Fx += C * ph.grav[0];
+                Fy += C * ph.grav[1];
+                Fz += C * ph.grav[2];
+            }
+            ux = mx + 0.5f * Fx;
+            uy = my + 0.5f * Fy;
+            uz = mz + 0.5f * Fz;
+            if (RHO) {
+                ux /= rho;
+                uy /= rho;
+                uz /= rho;
+                pt += 0.5f * (ux * grx + uy * gry + uz * grz);
+            }
+        }
+        const float uu = ux * ux + uy * uy + uz * uz;
+        const bool fluid = active && !solid;
+        const __amdgpu_buffer_rsrc_t fo = plane_rsrc(fdst, PL, c);
+        float itau = ph.inv_tau, fp3 = fpref3, ug = 0.f;
+        if (RHO) {
+            const bool liquid = C - (1.f - C1 - C) > 0.f;
+            itau = liquid ? ph.inv_tau : ph.inv_tau3;
+            fp3 = liquid ? fpref3 : 3.f * ph.fpref_gas;
+            ug = ux * grx + uy * gry + uz * grz;
+        }
+        const unsigned xo = fluid ? xb[1] : kOOB;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
+            const float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
+            const float si = s_i(cu, uu);
+            float feq, fi;
+            if (RHO) {
+                const float cg = L::cx[i] * grx + L::cy[i] * gry + L::cz[i] * grz - ug;
+                feq = L::w[i] * (pt + rho * si);
+                fi = fp3 * L::w[i] * (cF + (1.f / 3.f) * cg * si);
+            } else {
+                feq = L::w[i] * (pt + si);
+                fi = fp3 * L::w[i] * cF;
+            }
+            E::store(fo, xo, own_off + ES * (unsigned)(i * XP), fN[i] - (fN[i] - feq) * itau + fi);
+        }
+        const __amdgpu_buffer_rsrc_t go = plane_rsrc(gdst, PL, c);
+        const unsigned xg = active ? xb[1] : kOOB;
+        double moved = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
+            const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
+            const float gs = gC[i] - (gC[i] - geq) * ph.inv_taug;
+            moved += (double)E::store(go, xg, own_off + ES * (unsigned)(i * XP), gs);
+        }
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<char*>(g0dst) + RPL * c, (short)0, (int)RPL, kRsrcWord3);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, cC - moved), ro, (int)g0_off, 0, kNonTemporal);
+        bad |= active && (!isfinite(C) || !isfinite(uu));
+        // the lead plane becomes the next collision plane
+        cC = cN;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) gC[i] = gN[i];
+    }
+    if (bad) flag[0] = 1;
+}
+
+template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
+__device__ __forceinline__ void tile_step(const Geom& g, const Phys& ph, const void* __restrict__ fsrc,
+                                          const void* __restrict__ gsrc, void* __restrict__ fdst,
+                                          void* __restrict__ gdst, const float* __restrict__ c1g,
+                                          const uint8_t* __restrict__ mask, int* __restrict__ flag, int x0, int y0,
+                                          int z0, int TZ) {
+    if constexpr (E::lds_hold)
+        fused_tile<D, TXW, TY, STAGE, PULL, RHO, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, x0, y0, z0, TZ);
+    else
+        fused_tile_pipe<D, TXW, TY, STAGE, PULL, RHO, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, x0, y0, z0,
+                                                         TZ);
+}
+
 template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
 __global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per_eu(E::min_waves)))
     k_step_fused(Geom g, Phys ph, const void* __restrict__ fsrc, const void* __restrict__ gsrc,
@@ -454,7 +806,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per
     const int tile = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
     const int tile_x = tile % ntx, rest = tile / ntx;
     const int tile_y = rest % nty, tile_z = rest / nty;
-    fused_tile<D, TXW, TY, STAGE, PULL, RHO, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, tile_x * TX,
+    tile_step<D, TXW, TY, STAGE, PULL, RHO, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, tile_x * TX,
                                                 tile_y * TY, tile_z * TZ, TZ);
 }
 
@@ -478,7 +830,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per
         if (it >= nitems) break;  // uniform over the workgroup
         const BatchItem w = items[it];
         const BatchInst& d = inst[w.inst];
-        fused_tile<D, TXW, TY, 2, true, RHO, E>(d.geom, d.phys, d.f[parity], d.g[parity], d.f[1 - parity],
+        tile_step<D, TXW, TY, 2, true, RHO, E>(d.geom, d.phys, d.f[parity], d.g[parity], d.f[1 - parity],
                                                 d.g[1 - parity], d.c1, d.mask, d.flag, w.x0, w.y0, w.z0, TZ);
         __syncthreads();  // s_item is rewritten only after every wave has read it
     }
