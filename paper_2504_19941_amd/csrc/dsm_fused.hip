@@ -24,9 +24,10 @@
 // suffices.  Halo columns are the only recomputation (their loads hit in L2,
 // where the neighbouring tile of the same XCD reads the same lines), plus one
 // warm-up plane on each side of the march.  Two forms of the tile share this
-// scheme: fused_tile (FP16 elements, held g in LDS) issues each plane's loads
-// in its own phase 1; fused_tile_pipe (FP32) issues them one plane ahead,
-// before the previous plane's stores (see there).
+// scheme: fused_tile (3D with FP16 elements, held g in LDS) issues each
+// plane's loads in its own phase 1; fused_tile_pipe (every other lattice and
+// storage) issues them one plane ahead, before the previous plane's stores
+// (see there).
 //
 // Addressing.  Populations are stored row-interleaved: the Q values of the X
 // nodes of one row are contiguous, direction-major, each direction row padded
@@ -118,13 +119,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, l
 //
 // Occupancy.  The 3D tile holds the pulled g of its lead plane for one
 // iteration, until that plane's collision; in registers that brings it to
-// about 150 VGPRs, 3 waves per SIMD, one 8-wave tile per CU.  FP16 elements
-// are held instead as their raw bits in a two-slot LDS buffer of per-thread
-// cells (exact, 2 bytes each), and the FP16 tile kernels request 4 waves per
-// SIMD, so two tiles share a CU: the FP16 step moves half the bytes per
-// memory instruction and is latency-bound at one tile per CU.  The FP32 step
-// is bound by the memory system, gains nothing from a second tile, and keeps
-// its registers (min_waves 1: no request).
+// about 150 VGPRs (212 when pipelined), 2-3 waves per SIMD, one 8-wave tile
+// per CU.  With FP16 elements the 3D tile holds them instead as their raw
+// bits in a two-slot LDS buffer of per-thread cells (exact, 2 bytes each), and
+// the FP16 kernels request 4 waves per SIMD, so two tiles share a CU: the FP16
+// step moves half the bytes per memory instruction and is latency-bound at
+// one tile per CU (measured at 128^3: 96.7 us against 103.5 us pipelined).
+// The FP32 step is bound by the memory system, gains nothing from a second
+// tile, and keeps its registers (min_waves 1: no request).  The 2D tiles are
+// small enough (about 120 VGPRs) to be pipelined in either storage.
 struct F32 {
     using Raw = unsigned;
     static constexpr unsigned bytes = 4;
@@ -786,7 +789,7 @@ __device__ __forceinline__ void tile_step(const Geom& g, const Phys& ph, const v
                                           void* __restrict__ gdst, const float* __restrict__ c1g,
                                           const uint8_t* __restrict__ mask, int* __restrict__ flag, int x0, int y0,
                                           int z0, int TZ) {
-    if constexpr (E::lds_hold)
+    if constexpr (E::lds_hold && D == 3)
         fused_tile<D, TXW, TY, STAGE, PULL, RHO, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, x0, y0, z0, TZ);
     else
         fused_tile_pipe<D, TXW, TY, STAGE, PULL, RHO, E>(g, ph, fsrc, gsrc, fdst, gdst, c1g, mask, flag, x0, y0, z0,
