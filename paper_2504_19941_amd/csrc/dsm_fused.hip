@@ -198,6 +198,15 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
     const int y = y0 + yrow;  // uniform
     const bool active = (x < X) && (y < Y);
     const int rint = (1 + xseg * 64 + lane) + CRX * (HY + yrow);  // own region index
+    // Region indices of the columns x - 1, x, x + 1 in the own row.  A tile
+    // that spans its whole lattice row (x0 == 0, X <= TX) wraps them onto its
+    // own columns and needs no side halo (whose loads are uncoalesced: each
+    // of its lanes reads another row); other tiles use the halo columns at
+    // either end of the region.
+    const bool full_row = x0 == 0 && X <= T::TX;  // uniform
+    const int xl = xseg * 64 + lane;            // column within the tile
+    const int rrow = CRX * (HY + yrow);
+    const int rcol[3] = {full_row ? 1 + pmod(xl - 1, X) : xl, xl + 1, full_row ? 1 + pmod(xl + 1, X) : xl + 2};
 
     // Own column, wrapped (lanes beyond the lattice edge of a ragged tile
     // compute C of the wrapped column: the last real column needs it).
@@ -212,7 +221,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
     const int hyw = pmod(hbot ? y0 + TY : y0 - 1, Y);
     const int hyv[3] = {hyw == 0 ? Y - 1 : hyw - 1, hyw, hyw + 1 == Y ? 0 : hyw + 1};
     const int hreg = (1 + xseg * 64 + lane) + CRX * (hbot ? T::CRY - 1 : 0);
-    const bool side = wv == T::SIDE && lane < T::NSIDE;
+    const bool side = !full_row && wv == T::SIDE && lane < T::NSIDE;
     int srx = 0, sry = 0;
     if (side) T::side_pos(lane, srx, sry);
     const int sreg = srx + CRX * sry;
@@ -317,8 +326,9 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
         for (int i = 1; i < Q; i += 2) {
             const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);  // plane of x + c_i
             const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);  // plane of x - c_i
-            const int o = L::cx[i] + CRX * L::cy[i];
-            const float a = s_c[spl][rint + o], bm = s_c[smi][rint - o];
+            const int ip = rcol[1 + L::cx[i]] + rrow + CRX * L::cy[i];  // x + c_i
+            const int im = rcol[1 - L::cx[i]] + rrow - CRX * L::cy[i];  // x - c_i
+            const float a = s_c[spl][ip], bm = s_c[smi][im];
             lc += L::w[i] * ((a - C) + (bm - C));
             const float d = a - bm;
             gx += L::w[i] * L::cx[i] * d;
@@ -335,12 +345,12 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
             for (int i = 1; i < Q; i += 2) {
                 const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);
                 const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);
-                const int o = L::cx[i] + CRX * L::cy[i];
-                const float a1 = s_c1[spl][rint + o], b1 = s_c1[smi][rint - o];
+                const int ip = rcol[1 + L::cx[i]] + rrow + CRX * L::cy[i];
+                const int im = rcol[1 - L::cx[i]] + rrow - CRX * L::cy[i];
+                const float a1 = s_c1[spl][ip], b1 = s_c1[smi][im];
                 l1 += L::w[i] * ((a1 - C1) + (b1 - C1));
                 if (RHO) {
-                    const float d = local_density(ph, s_c[spl][rint + o], a1) -
-                                    local_density(ph, s_c[smi][rint - o], b1);
+                    const float d = local_density(ph, s_c[spl][ip], a1) - local_density(ph, s_c[smi][im], b1);
                     grx += L::w[i] * L::cx[i] * d;
                     gry += L::w[i] * L::cy[i] * d;
                     grz += L::w[i] * L::cz[i] * d;
@@ -501,6 +511,15 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
     const int y = y0 + yrow;  // uniform
     const bool active = (x < X) && (y < Y);
     const int rint = (1 + xseg * 64 + lane) + CRX * (HY + yrow);  // own region index
+    // Region indices of the columns x - 1, x, x + 1 in the own row.  A tile
+    // that spans its whole lattice row (x0 == 0, X <= TX) wraps them onto its
+    // own columns and needs no side halo (whose loads are uncoalesced: each
+    // of its lanes reads another row); other tiles use the halo columns at
+    // either end of the region.
+    const bool full_row = x0 == 0 && X <= T::TX;  // uniform
+    const int xl = xseg * 64 + lane;            // column within the tile
+    const int rrow = CRX * (HY + yrow);
+    const int rcol[3] = {full_row ? 1 + pmod(xl - 1, X) : xl, xl + 1, full_row ? 1 + pmod(xl + 1, X) : xl + 2};
 
     const int xv[3] = {pmod(x - 1, X), pmod(x, X), pmod(x + 1, X)};  // x-1, x, x+1
     const unsigned xb[3] = {ES * xv[0], ES * xv[1], ES * xv[2]};        // as byte offsets
@@ -512,7 +531,7 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
     const int hyw = pmod(hbot ? y0 + TY : y0 - 1, Y);
     const int hyv[3] = {hyw == 0 ? Y - 1 : hyw - 1, hyw, hyw + 1 == Y ? 0 : hyw + 1};
     const int hreg = (1 + xseg * 64 + lane) + CRX * (hbot ? T::CRY - 1 : 0);
-    const bool side = wv == T::SIDE && lane < T::NSIDE;
+    const bool side = !full_row && wv == T::SIDE && lane < T::NSIDE;
     int srx = 0, sry = 0;
     if (side) T::side_pos(lane, srx, sry);
     const int sreg = srx + CRX * sry;
@@ -667,8 +686,9 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
         for (int i = 1; i < Q; i += 2) {
             const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);  // plane of x + c_i
             const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);  // plane of x - c_i
-            const int o = L::cx[i] + CRX * L::cy[i];
-            const float a = s_c[spl][rint + o], bm = s_c[smi][rint - o];
+            const int ip = rcol[1 + L::cx[i]] + rrow + CRX * L::cy[i];  // x + c_i
+            const int im = rcol[1 - L::cx[i]] + rrow - CRX * L::cy[i];  // x - c_i
+            const float a = s_c[spl][ip], bm = s_c[smi][im];
             lc += L::w[i] * ((a - C) + (bm - C));
             const float d = a - bm;
             gx += L::w[i] * L::cx[i] * d;
@@ -685,12 +705,12 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
             for (int i = 1; i < Q; i += 2) {
                 const int spl = L::cz[i] < 0 ? sm_ : (L::cz[i] > 0 ? sp : s0);
                 const int smi = L::cz[i] < 0 ? sp : (L::cz[i] > 0 ? sm_ : s0);
-                const int o = L::cx[i] + CRX * L::cy[i];
-                const float a1 = s_c1[spl][rint + o], b1 = s_c1[smi][rint - o];
+                const int ip = rcol[1 + L::cx[i]] + rrow + CRX * L::cy[i];
+                const int im = rcol[1 - L::cx[i]] + rrow - CRX * L::cy[i];
+                const float a1 = s_c1[spl][ip], b1 = s_c1[smi][im];
                 l1 += L::w[i] * ((a1 - C1) + (b1 - C1));
                 if (RHO) {
-                    const float d = local_density(ph, s_c[spl][rint + o], a1) -
-                                    local_density(ph, s_c[smi][rint - o], b1);
+                    const float d = local_density(ph, s_c[spl][ip], a1) - local_density(ph, s_c[smi][im], b1);
                     grx += L::w[i] * L::cx[i] * d;
                     gry += L::w[i] * L::cy[i] * d;
                     grz += L::w[i] * L::cz[i] * d;
