@@ -199,8 +199,9 @@ long long dsm_step_count(const dsm_sim* s);
  * 2D: 0 = 256, 1 = 128, 2 = 64 columns) and the number of planes (1..4096)
  * each workgroup marches through along the slowest axis.  Every choice
  * computes bit-identical populations (each node's arithmetic does not depend
- * on the tile).  Defaults: 3D variant 2 with 16 planes (8 with FP16
- * storage), 2D variant 0 with 16 planes.
+ * on the tile).  Defaults: 3D variant 2 with 16 planes, or 32 when the
+ * lattice has enough 128x4 tiles to give every compute unit whole rounds of
+ * 32-plane marches (8 planes with FP16 storage); 2D variant 0 with 16 planes.
  * Errors: DSM_EINVAL. */
 int dsm_set_tiling(dsm_sim* s, int variant, int planes);
 int dsm_tiling_variants(int dim);
