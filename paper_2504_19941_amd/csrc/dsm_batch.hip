@@ -307,28 +307,29 @@ int check_sched(int dim, const dsm_batch_schedule* s) {
 // Plane counts the tuner considers.
 constexpr int kTunePlanes[] = {8, 16, 32, 64, 128};
 
-// Relative cost of one wave marching one plane, per tile variant (index:
-// variant).  Fitted to the batched kernel's measured step times on MI355X
-// over every schedule of a 512-lattice D2Q9 set (2D: 256/128/64 columns) and
-// measured on 3D sets (64x4/64x8/128x4 columns): a wave of a wider tile is
-// cheaper, because the tile's workgroup shares the C halo and the barrier of
-// each plane among more waves.
-constexpr double kWaveCost[2][3] = {{1.0, 1.16, 1.30}, {1.08, 1.06, 1.0}};
-
+// Model constants per lattice type (index 0: 2D, 1: 3D), fitted to the
+// batched kernel's measured step times on MI355X over every schedule (3 tile
+// variants x 5 plane counts) of a 512-lattice D2Q9 set and of a 24-job set of
+// the served form's 3D lattices.
+// Relative cost of one wave marching one plane, per tile variant (2D:
+// 256/128/64 columns; 3D: 64x4/64x8/128x4 columns).
+constexpr double kWaveCost[2][3] = {{1.0, 1.16, 1.30}, {1.0, 1.02, 0.89}};
+// Cost of each of the two planes an item marches beyond its own (to fill the
+// C ring before its first collision), as a share of a full plane: they pull g
+// only, mostly from L2, where the neighbouring items of the same lattice have
+// just read them; in 3D they also pull the halo rows and columns.
+constexpr double kFillShare[2] = {0.0, 0.36};
 // Tail of a step: the share of the longest item that outlasts the drained
-// queue (fitted with the wave costs above).
-constexpr double kTailShare = 0.0625;
+// queue.
+constexpr double kTailShare[2] = {0.0625, 0.095};
 
 // Modelled duration of one batched step of the members of one lattice type
 // under a schedule, in units of one wave marching one plane.  A wave costs
-// the same whether or not all of its lanes hold lattice columns.  The two
-// planes each item marches beyond its own (to fill the C ring before its
-// first collision) pull g only, mostly from L2, where the neighbouring items
-// of the same lattice, queued next to it, have just read them: the fit
-// leaves them no measurable cost, so they are not charged.  The dynamic
-// queue, fed costliest item first, keeps every resident wave busy until the
-// list is drained, so the step lasts the total work over the resident waves
-// plus a tail of kTailShare of the longest item.
+// the same whether or not all of its lanes hold lattice columns; each item's
+// two fill planes cost kFillShare of a plane each.  The dynamic queue, fed
+// costliest item first, keeps every resident wave busy until the list is
+// drained, so the step lasts the total work over the resident waves plus a
+// tail of kTailShare of the longest item.
 double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
     int tx = 0, ty = 0;
     fused_tile_shape(dim, variant, &tx, &ty);
@@ -342,12 +343,13 @@ double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
             const Geom& g = m->geom;
             const double tiles = (double)((g.X + tx - 1) / tx) * (double)((g.Y + ty - 1) / ty);
             const int full = g.Z / planes, tail = g.Z % planes;
-            total += tiles * waves_per_item * ((double)full * planes + tail);
-            longest = std::max(longest, (double)(full ? planes : tail));
+            const double fill = 2.0 * kFillShare[dim - 2];
+            total += tiles * waves_per_item * ((double)full * (planes + fill) + (tail ? tail + fill : 0.0));
+            longest = std::max(longest, (full ? planes : tail) + fill);
         }
         const int per_cu = batch_blocks_per_cu(dim, variant, b->half, t & 1);
         const double resident_waves = (double)b->cus * per_cu * waves_per_item;
-        cost += kWaveCost[dim - 2][variant] * (total / resident_waves + kTailShare * longest);
+        cost += kWaveCost[dim - 2][variant] * (total / resident_waves + kTailShare[dim - 2] * longest);
     }
     return cost;
 }
