@@ -123,7 +123,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, l
 // about 150 VGPRs (212 when pipelined), 2-3 waves per SIMD, one 8-wave tile
 // per CU.  With FP16 elements the 3D tile holds them instead as their raw
 // bits in a two-slot LDS buffer of per-thread cells (exact, 2 bytes each), and
-// the FP16 kernels request 4 waves per SIMD, so two tiles share a CU: the FP16
+// the 3D FP16 kernels request 4 waves per SIMD, so two tiles share a CU: the FP16
 // step moves half the bytes per memory instruction and is latency-bound at
 // one tile per CU (measured at 128^3: 7 % faster than the pipelined tile at
 // one tile per CU).
@@ -819,7 +819,7 @@ __device__ __forceinline__ void tile_step(const Geom& g, const Phys& ph, const v
 }
 
 template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
-__global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per_eu(E::min_waves)))
+__global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per_eu(D == 3 ? E::min_waves : 1)))
     k_step_fused(Geom g, Phys ph, const void* __restrict__ fsrc, const void* __restrict__ gsrc,
                  void* __restrict__ fdst, void* __restrict__ gdst, const float* __restrict__ c1g,
                  const uint8_t* __restrict__ mask, int* __restrict__ flag, int TZ, int ntx, int nty) {
@@ -844,7 +844,7 @@ __global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per
 // geometry, parameters and buffers come from a descriptor table, with the
 // two buffer pairs exchanged by the step parity.
 template <int D, int TXW, int TY, bool RHO, typename E>
-__global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per_eu(E::min_waves)))
+__global__ void __launch_bounds__(64 * TXW * TY) __attribute__((amdgpu_waves_per_eu(D == 3 ? E::min_waves : 1)))
     k_step_batch(const BatchInst* __restrict__ inst, const BatchItem* __restrict__ items, int nitems,
                  int* __restrict__ counter, int parity, int TZ) {
     __shared__ int s_item;
