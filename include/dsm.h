@@ -201,7 +201,8 @@ long long dsm_step_count(const dsm_sim* s);
  * computes bit-identical populations (each node's arithmetic does not depend
  * on the tile).  Defaults: 3D variant 2 with 16 planes, or 32 when the
  * lattice has enough 128x4 tiles to give every compute unit whole rounds of
- * 32-plane marches (8 planes with FP16 storage); 2D variant 0 with 16 planes.
+ * 32-plane marches; with FP16 storage 8 planes, or 16 when every compute unit
+ * gets two tiles in whole rounds; 2D variant 0 with 16 planes.
  * Errors: DSM_EINVAL. */
 int dsm_set_tiling(dsm_sim* s, int variant, int planes);
 int dsm_tiling_variants(int dim);

@@ -341,19 +341,21 @@ int check_flag(dsm_sim* s) {
 
 }  // namespace
 
-// Default march of the 3D FP32 tile (variant 2, one tile per CU): 32 planes
-// when that grid still gives every CU a tile and whole rounds of tiles (the
-// last round at least 80 % busy), else 16.  Longer marches re-read fewer fill
-// planes: on MI355X 128 x 256 x 128 runs at 17.5 GLUPS with 32 planes against
-// 16.9 with 16, and 256 x 256 x 192 at 16.7 against 15.9; 128^3 has too few
-// tiles for 32.
-int default_planes_3d(const Geom& g, int cus) {
+// Default march of the 3D tile (variant 2): the longer of two plane counts
+// when its grid still fills every tile slot of the chip (slots = CUs x tiles
+// resident per CU) in whole rounds, the last at least 80 % busy; else the
+// shorter.  Longer marches re-read fewer fill planes.  Measured on MI355X:
+// FP32 (one tile per CU) 32 planes over 16, e.g. 128 x 256 x 128 at 17.5
+// GLUPS against 16.9 and 256 x 256 x 192 at 16.7 against 15.9; FP16 (two
+// tiles per CU) 16 planes over 8, e.g. 256 x 256 x 192 at 24.2 against 22.9;
+// 128^3 has too few tiles for the longer march in either storage.
+int default_planes_3d(const Geom& g, int slots, int longer, int shorter) {
     int tx = 0, ty = 0;
     fused_tile_shape(3, 2, &tx, &ty);
     const long long tiles = (long long)((g.X + tx - 1) / tx) * ((g.Y + ty - 1) / ty);
-    const long long n = tiles * ((g.Z + 31) / 32);
-    const long long rounds = (n + cus - 1) / cus;
-    return cus > 0 && n >= cus && (double)n >= 0.8 * (double)(rounds * cus) ? 32 : 16;
+    const long long n = tiles * ((g.Z + longer - 1) / longer);
+    const long long rounds = (n + slots - 1) / slots;
+    return slots > 0 && n >= slots && (double)n >= 0.8 * (double)(rounds * slots) ? longer : shorter;
 }
 
 extern "C" {
@@ -417,11 +419,12 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     // FP16 3D tiles run two per CU (see the tile kernels' occupancy), so
     // shorter marches keep twice as many tiles in flight
     s->tile_planes = p->dim == 3 && s->half ? 8 : 16;
-    if (p->dim == 3 && !s->half) {
+    if (p->dim == 3) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            s->tile_planes = default_planes_3d(s->geom, cus);
+            s->tile_planes = s->half ? default_planes_3d(s->geom, 2 * cus, 16, 8)
+                                     : default_planes_3d(s->geom, cus, 32, 16);
     }
     auto cleanup = [&](int rc) {
         delete s;
