@@ -64,7 +64,56 @@ __device__ __forceinline__ int pmod(int a, int n) {
     return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ float s_i(float cu, float uu) { return 3.f * cu + 4.5f * cu * cu - 1.5f * uu; }
+// Products with lattice vectors, whose components are -1, 0 or 1: the kept
+// terms are +-v exactly, summed in x, y, z order, and the zero terms are left
+// out.  The full product sum rounds the same way, since the terms it adds
+// besides these are exact zeros (the sign of an exact-zero result aside).
+template <typename L>
+__device__ __forceinline__ float cdot(int i, float vx, float vy, float vz) {
+    const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+    const float v[3] = {vx, vy, vz};
+    float s = 0.f;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (c[k] == 0) continue;
+        const float t = c[k] > 0 ? v[k] : -v[k];
+        s = any ? s + t : t;
+        any = true;
+    }
+    return s;
+}
+// a += c_i v, componentwise
+template <typename L>
+__device__ __forceinline__ void cacc(int i, float v, float& ax, float& ay, float& az) {
+    if (L::cx[i]) ax = L::cx[i] > 0 ? ax + v : ax - v;
+    if (L::cy[i]) ay = L::cy[i] > 0 ? ay + v : ay - v;
+    if (L::cz[i]) az = L::cz[i] > 0 ? az + v : az - v;
+}
+// a += (w_i c_i) v, componentwise
+template <typename L>
+__device__ __forceinline__ void wacc(int i, float v, float& ax, float& ay, float& az) {
+    if (L::cx[i]) ax += L::w[i] * L::cx[i] * v;
+    if (L::cy[i]) ay += L::w[i] * L::cy[i] * v;
+    if (L::cz[i]) az += L::w[i] * L::cz[i] * v;
+}
+// s_i(u) = 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u.u for the directions in order.
+// Direction i + 1 (odd i) is the opposite of i, so its two c.u terms are
+// those of i with the first negated: (4.5 (c.u)^2 - 3 c.u) - 1.5 u.u, rounded
+// as computing it afresh would round it.
+template <typename L>
+struct SeqS {
+    float t1 = 0.f, t3 = 0.f;  // 3 c.u and 4.5 (c.u)^2 of the last odd direction
+    __device__ __forceinline__ float next(int i, float ux, float uy, float uz, float uu15) {
+        if (i == 0 || (i & 1)) {
+            const float cu = cdot<L>(i, ux, uy, uz);
+            t1 = 3.f * cu;
+            t3 = 4.5f * cu * cu;
+            return t1 + t3 - uu15;
+        }
+        return t3 - t1 - uu15;
+    }
+};
 
 template <int D, int TXW, int TY>
 struct Tile {
@@ -155,8 +204,12 @@ struct F16 {  // FP16 holding value * kHalfScale
     static __device__ __forceinline__ Raw load_raw(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
         return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
     }
+    // h / kHalfScale as one mixed-precision FMA (convert, scale, add +0).  The
+    // scale is a power of two, so the product is exact; the +0 turns a -0
+    // into +0 and changes nothing else.  Stores return this same value, so
+    // what a step counts as stored is what the next step reads.
     static __device__ __forceinline__ float value(Raw h) {
-        return __half2float(__ushort_as_half(h)) * (1.f / kHalfScale);
+        return __builtin_fmaf(__half2float(__ushort_as_half(h)), 1.f / kHalfScale, 0.f);
     }
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
         return value(load_raw(r, voff, soff));
@@ -164,7 +217,7 @@ struct F16 {  // FP16 holding value * kHalfScale
     static __device__ __forceinline__ float store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
         const __half h = __float2half(v * kHalfScale);
         __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(h), r, (int)voff, (int)soff, kNonTemporal);
-        return __half2float(h) * (1.f / kHalfScale);
+        return value(__half_as_ushort(h));
     }
 };
 
@@ -255,6 +308,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
         {
             const long long node = xv[1] + X * ((long long)yv[1] + (long long)Y * lz);
             const double r0 = g0src[xv[1] + XP * ((long long)yv[1] + (long long)Y * lz)];
+            const float c1v = STAGE == 2 ? c1g[node] : 0.f;
             typename E::Raw raw[Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
@@ -271,49 +325,53 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
             }
             cload = r0 + acc;
             s_c[sl][rint] = (float)cload;
-            if (STAGE == 2) s_c1[sl][rint] = c1g[node];
+            if (STAGE == 2) s_c1[sl][rint] = c1v;
         }
         // lead plane, halo columns (same summation order as the own column)
         if (row_halo) {
             const long long node = xv[1] + X * ((long long)hyw + (long long)Y * lz);
             const double r0 = g0src[xv[1] + XP * ((long long)hyw + (long long)Y * lz)];
-            float h[Q];
+            const float c1v = STAGE == 2 ? c1g[node] : 0.f;
+            typename E::Raw h[Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                h[i] = E::load(gl[sz], xb[sx], ES * (unsigned)(hyv[sy] * QX + i * XP));
+                h[i] = E::load_raw(gl[sz], xb[sx], ES * (unsigned)(hyv[sy] * QX + i * XP));
             }
+            __builtin_amdgcn_sched_barrier(0);  // every pull in flight before the first is used
             double acc = 0.0;
 #pragma unroll
-            for (int i = 1; i < Q; ++i) acc += (double)h[i];
+            for (int i = 1; i < Q; ++i) acc += (double)E::value(h[i]);
             s_c[sl][hreg] = (float)(r0 + acc);
-            if (STAGE == 2) s_c1[sl][hreg] = c1g[node];
+            if (STAGE == 2) s_c1[sl][hreg] = c1v;
         } else if (side) {
             const long long node = sxw + X * ((long long)syw + (long long)Y * lz);
             const double r0 = g0src[sxw + XP * ((long long)syw + (long long)Y * lz)];
-            float h[Q];
+            const float c1v = STAGE == 2 ? c1g[node] : 0.f;
+            typename E::Raw h[Q];
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                h[i] = E::load(gl[sz], ES * (unsigned)(syv[sy] * QX + i * XP + sxv[sx]), 0u);
+                h[i] = E::load_raw(gl[sz], ES * (unsigned)(syv[sy] * QX + i * XP + sxv[sx]), 0u);
             }
+            __builtin_amdgcn_sched_barrier(0);
             double acc = 0.0;
 #pragma unroll
-            for (int i = 1; i < Q; ++i) acc += (double)h[i];
+            for (int i = 1; i < Q; ++i) acc += (double)E::value(h[i]);
             s_c[sl][sreg] = (float)(r0 + acc);
-            if (STAGE == 2) s_c1[sl][sreg] = c1g[node];
+            if (STAGE == 2) s_c1[sl][sreg] = c1v;
         }
-        // collision plane: f (in flight across the barrier)
+        // collision plane: f, in flight across the barrier (raw until after it)
         bool solid = false;
         if (STAGE == 2 && collide) solid = s_c1[(j + 3) & 3][rint] > 0.5f;
-        float f[Q];
+        typename E::Raw fr[Q];
         if (collide && !solid) {
             const __amdgpu_buffer_rsrc_t fc[3] = {plane_rsrc(fsrc, PL, zc[0]), plane_rsrc(fsrc, PL, zc[1]),
                                                   plane_rsrc(fsrc, PL, zc[2])};
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int sy = PULL ? 1 - L::cy[i] : 1, sz = PULL ? 1 - L::cz[i] : 1, sx = PULL ? 1 - L::cx[i] : 1;
-                f[i] = E::load(fc[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * XP));
+                fr[i] = E::load_raw(fc[sz], xb[sx], ES * (unsigned)(yv[sy] * QX + i * XP));
             }
         }
         __syncthreads();
@@ -333,9 +391,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
             const float a = s_c[spl][ip], bm = s_c[smi][im];
             lc += L::w[i] * ((a - C) + (bm - C));
             const float d = a - bm;
-            gx += L::w[i] * L::cx[i] * d;
-            gy += L::w[i] * L::cy[i] * d;
-            gz += L::w[i] * L::cz[i] * d;
+            wacc<L>(i, d, gx, gy, gz);
         }
         lc *= 6.f;
         float mu, C1 = 0.f;
@@ -353,9 +409,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
                 l1 += L::w[i] * ((a1 - C1) + (b1 - C1));
                 if (RHO) {
                     const float d = local_density(ph, s_c[spl][ip], a1) - local_density(ph, s_c[smi][im], b1);
-                    grx += L::w[i] * L::cx[i] * d;
-                    gry += L::w[i] * L::cy[i] * d;
-                    grz += L::w[i] * L::cz[i] * d;
+                    wacc<L>(i, d, grx, gry, grz);
                 }
             }
             l1 *= 6.f;
@@ -377,6 +431,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
             if (C > 1.f) mu -= 2.f * ph.omega * (1.f - C);
         }
         float ux = 0.f, uy = 0.f, uz = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f, pt = 0.f;
+        float f[Q];
         if (!solid) {
             Fx = mu * 3.f * gx;
             Fy = mu * 3.f * gy;
@@ -387,12 +442,19 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
                 Fz += C * ph.grav[2];
             }
             float mx = 0.f, my = 0.f, mz = 0.f;
+            // The f pulls are consumed from here on.  The empty asm marks their
+            // raw values as changed at this point, so that their conversion (and
+            // the wait for them) cannot be hoisted above the barrier.  With a
+            // density contrast the longer stencil leaves no registers for that.
+            if (!RHO) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(fr[i]));
+            }
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
+                f[i] = E::value(fr[i]);
                 pt += f[i];
-                mx += L::cx[i] * f[i];
-                my += L::cy[i] * f[i];
-                mz += L::cz[i] * f[i];
+                cacc<L>(i, f[i], mx, my, mz);
             }
             ux = mx + 0.5f * Fx;
             uy = my + 0.5f * Fy;
@@ -406,6 +468,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
             }
         }
         const float uu = ux * ux + uy * uy + uz * uz;
+        const float uu15 = 1.5f * uu;
         const unsigned own_off = ES * (unsigned)(yv[1] * QX);
         if (!solid) {
             const __amdgpu_buffer_rsrc_t fo = plane_rsrc(fdst, PL, c);
@@ -417,15 +480,15 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
                 fp3 = liquid ? fpref3 : 3.f * ph.fpref_gas;
                 ug = ux * grx + uy * gry + uz * grz;
             }
+            SeqS<L> sq;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
-                const float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
-                const float si = s_i(cu, uu);
+                const float si = sq.next(i, ux, uy, uz, uu15);
+                const float cF = cdot<L>(i, Fx, Fy, Fz);
                 float feq, fi;
                 if (RHO) {
                     // F_i = (1 - 1/2tau) w_i [((c_i - u) . grad rho) s_i + c_i . F / c_s^2]
-                    const float cg = L::cx[i] * grx + L::cy[i] * gry + L::cz[i] * grz - ug;
+                    const float cg = cdot<L>(i, grx, gry, grz) - ug;
                     feq = L::w[i] * (pt + rho * si);
                     fi = fp3 * L::w[i] * (cF + (1.f / 3.f) * cg * si);
                 } else {
@@ -439,11 +502,18 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
         // moving populations first; the rest population takes what is left of
         // C (FP64), so the stored populations of the node keep its C
         double moved = 0.0;
+        // held g: every LDS read issued before the first is used
+        typename E::Raw gh[Q];
+        if (E::lds_hold) {
+#pragma unroll
+            for (int i = 1; i < Q; ++i) gh[i] = s_gh[(j + 1) & 1][i - 1][t];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        SeqS<L> sg;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
-            const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
-            const float gc = E::lds_hold ? E::value(s_gh[(j + 1) & 1][i - 1][t]) : gcoll[i];
+            const float geq = L::w[i] * mu + L::w[i] * C * sg.next(i, ux, uy, uz, uu15);
+            const float gc = E::lds_hold ? E::value(gh[i]) : gcoll[i];
             const float gs = gc - (gc - geq) * ph.inv_taug;
             moved += (double)E::store(go, xb[1], own_off + ES * (unsigned)(i * XP), gs);
         }
@@ -670,9 +740,7 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 pt += fN[i];
-                mx += L::cx[i] * fN[i];
-                my += L::cy[i] * fN[i];
-                mz += L::cz[i] * fN[i];
+                cacc<L>(i, fN[i], mx, my, mz);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -693,9 +761,7 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
             const float a = s_c[spl][ip], bm = s_c[smi][im];
             lc += L::w[i] * ((a - C) + (bm - C));
             const float d = a - bm;
-            gx += L::w[i] * L::cx[i] * d;
-            gy += L::w[i] * L::cy[i] * d;
-            gz += L::w[i] * L::cz[i] * d;
+            wacc<L>(i, d, gx, gy, gz);
         }
         lc *= 6.f;
         float mu, C1 = 0.f;
@@ -713,9 +779,7 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
                 l1 += L::w[i] * ((a1 - C1) + (b1 - C1));
                 if (RHO) {
                     const float d = local_density(ph, s_c[spl][ip], a1) - local_density(ph, s_c[smi][im], b1);
-                    grx += L::w[i] * L::cx[i] * d;
-                    gry += L::w[i] * L::cy[i] * d;
-                    grz += L::w[i] * L::cz[i] * d;
+                    wacc<L>(i, d, grx, gry, grz);
                 }
             }
             l1 *= 6.f;
@@ -757,6 +821,7 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
             }
         }
         const float uu = ux * ux + uy * uy + uz * uz;
+        const float uu15 = 1.5f * uu;
         const bool fluid = active && !solid;
         const __amdgpu_buffer_rsrc_t fo = plane_rsrc(fdst, PL, c);
         float itau = ph.inv_tau, fp3 = fpref3, ug = 0.f;
@@ -767,14 +832,14 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
             ug = ux * grx + uy * gry + uz * grz;
         }
         const unsigned xo = fluid ? xb[1] : kOOB;
+        SeqS<L> sq;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
-            const float cF = L::cx[i] * Fx + L::cy[i] * Fy + L::cz[i] * Fz;
-            const float si = s_i(cu, uu);
+            const float si = sq.next(i, ux, uy, uz, uu15);
+            const float cF = cdot<L>(i, Fx, Fy, Fz);
             float feq, fi;
             if (RHO) {
-                const float cg = L::cx[i] * grx + L::cy[i] * gry + L::cz[i] * grz - ug;
+                const float cg = cdot<L>(i, grx, gry, grz) - ug;
                 feq = L::w[i] * (pt + rho * si);
                 fi = fp3 * L::w[i] * (cF + (1.f / 3.f) * cg * si);
             } else {
@@ -786,10 +851,10 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
         const __amdgpu_buffer_rsrc_t go = plane_rsrc(gdst, PL, c);
         const unsigned xg = active ? xb[1] : kOOB;
         double moved = 0.0;
+        SeqS<L> sg;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const float cu = L::cx[i] * ux + L::cy[i] * uy + L::cz[i] * uz;
-            const float geq = L::w[i] * mu + L::w[i] * C * s_i(cu, uu);
+            const float geq = L::w[i] * mu + L::w[i] * C * sg.next(i, ux, uy, uz, uu15);
             const float gs = gC[i] - (gC[i] - geq) * ph.inv_taug;
             moved += (double)E::store(go, xg, own_off + ES * (unsigned)(i * XP), gs);
         }
