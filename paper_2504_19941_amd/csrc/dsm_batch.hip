@@ -330,6 +330,16 @@ constexpr double kTailShare[2] = {0.0625, 0.095};
 // costliest item first, keeps every resident wave busy until the list is
 // drained, so the step lasts the total work over the resident waves plus a
 // tail of kTailShare of the longest item.
+// One member's work (wave-planes) and its longest item under a tiling.
+void member_work(const Geom& g, int dim, int tx, int ty, int planes, double* total, double* longest) {
+    const double waves_per_item = (double)(tx / 64) * ty;
+    const double tiles = (double)((g.X + tx - 1) / tx) * (double)((g.Y + ty - 1) / ty);
+    const int full = g.Z / planes, tail = g.Z % planes;
+    const double fill = 2.0 * kFillShare[dim - 2];
+    *total += tiles * waves_per_item * ((double)full * (planes + fill) + (tail ? tail + fill : 0.0));
+    *longest = std::max(*longest, (full ? planes : tail) + fill);
+}
+
 double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
     int tx = 0, ty = 0;
     fused_tile_shape(dim, variant, &tx, &ty);
@@ -338,15 +348,8 @@ double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
     for (int t = 2 * type_index(dim); t < 2 * type_index(dim) + 2; ++t) {
         if (!b->present[t]) continue;
         double total = 0.0, longest = 0.0;
-        for (const dsm_sim* m : b->sims) {
-            if (group_of(m) != t) continue;
-            const Geom& g = m->geom;
-            const double tiles = (double)((g.X + tx - 1) / tx) * (double)((g.Y + ty - 1) / ty);
-            const int full = g.Z / planes, tail = g.Z % planes;
-            const double fill = 2.0 * kFillShare[dim - 2];
-            total += tiles * waves_per_item * ((double)full * (planes + fill) + (tail ? tail + fill : 0.0));
-            longest = std::max(longest, (full ? planes : tail) + fill);
-        }
+        for (const dsm_sim* m : b->sims)
+            if (group_of(m) == t) member_work(m->geom, dim, tx, ty, planes, &total, &longest);
         const int per_cu = batch_blocks_per_cu(dim, variant, b->half, t & 1);
         const double resident_waves = (double)b->cus * per_cu * waves_per_item;
         cost += kWaveCost[dim - 2][variant] * (total / resident_waves + kTailShare[dim - 2] * longest);
@@ -355,6 +358,15 @@ double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
 }
 
 }  // namespace
+
+double dsm::lattice_schedule_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus) {
+    int tx = 0, ty = 0;
+    fused_tile_shape(dim, variant, &tx, &ty);
+    double total = 0.0, longest = 0.0;
+    member_work(g, dim, tx, ty, planes, &total, &longest);
+    const double resident_waves = (double)cus * blocks_per_cu * (double)(tx / 64) * ty;
+    return kWaveCost[dim - 2][variant] * (total / resident_waves + kTailShare[dim - 2] * longest);
+}
 
 extern "C" {
 

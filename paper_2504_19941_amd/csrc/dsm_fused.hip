@@ -1070,6 +1070,36 @@ int batch_blocks_per_cu(int dim, int variant, int half, int rho) {
     }
 }
 
+namespace {
+template <int D, int TXW, int TY, bool RHO, typename E>
+int fused_occupancy() {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_fused<D, TXW, TY, 2, true, RHO, E>,
+                                                                      64 * TXW * TY, 0);
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+template <int D, int TXW, int TY>
+int fused_occupancy_tile(int half, int rho) {
+    if (rho) return half ? fused_occupancy<D, TXW, TY, true, F16>() : fused_occupancy<D, TXW, TY, true, F32>();
+    return half ? fused_occupancy<D, TXW, TY, false, F16>() : fused_occupancy<D, TXW, TY, false, F32>();
+}
+}  // namespace
+
+int fused_blocks_per_cu(int dim, int variant, int half, int rho) {
+    if (dim == 2) {
+        switch (variant) {
+            case 1: return fused_occupancy_tile<2, 2, 1>(half, rho);
+            case 2: return fused_occupancy_tile<2, 1, 1>(half, rho);
+            default: return fused_occupancy_tile<2, 4, 1>(half, rho);
+        }
+    }
+    switch (variant) {
+        case 1: return fused_occupancy_tile<3, 1, 8>(half, rho);
+        case 2: return fused_occupancy_tile<3, 2, 4>(half, rho);
+        default: return fused_occupancy_tile<3, 1, 4>(half, rho);
+    }
+}
+
 hipError_t launch_step_fused(int dim, const Geom& g, const Phys& ph, Pop fsrc, Pop gsrc, Pop fdst, Pop gdst,
                              const float* c1, const uint8_t* mask, int pull, int* flag,
                              int variant, int TZ, hipStream_t st) {

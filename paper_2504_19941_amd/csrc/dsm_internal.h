@@ -117,6 +117,12 @@ void fused_tile_shape(int dim, int variant, int* tx, int* ty);
 hipError_t launch_step_batch(int dim, int variant, int half, int rho, const BatchInst* inst, const BatchItem* items,
                              int nitems, int* counter, int grid, int parity, int TZ, hipStream_t st);
 int batch_blocks_per_cu(int dim, int variant, int half, int rho);
+// workgroups of the single-lattice fused kernel (fluid stage) resident per CU
+int fused_blocks_per_cu(int dim, int variant, int half, int rho);
+// Modelled duration of one step of one lattice under a tiling (dsm_batch.hip):
+// the schedule model of the batched step with this lattice as its only member
+// and blocks_per_cu workgroups resident per CU.
+double lattice_schedule_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus);
 hipError_t launch_bounce_batch(const BatchInst* inst, const BatchChunk* chunks, int nchunks, int parity,
                                int* counters, int ncounters, hipStream_t st);
 hipError_t launch_batch_flags(const BatchInst* inst, int count, int* out, hipStream_t st);
