@@ -202,11 +202,13 @@ long long dsm_step_count(const dsm_sim* s);
  * on the tile).  Defaults: 3D variant 2 with 16 planes, or 32 when the
  * lattice has enough 128x4 tiles to give every compute unit whole rounds of
  * 32-plane marches; with FP16 storage 8 planes, or 16 when every compute unit
- * gets two tiles in whole rounds; 2D variant 0 with 16 planes.  dsm_create
- * replaces that default by another variant and a march of 8, 16 or 32 planes
- * when a model of the step's duration (work over resident waves, per-variant
- * wave cost, fill planes and tail) predicts it at least 10 % faster, as for
- * narrow 2D rows, small cubes and rows just wider than a tile.
+ * gets two tiles in whole rounds; 2D variant 0 with 16 planes, or 8 when the
+ * lattice has too few 256-column tiles to give every compute unit whole
+ * rounds of 16-plane marches.  dsm_create replaces that default by another
+ * variant and a march of 8, 16 or 32 planes when a model of the step's
+ * duration (work over resident waves, per-variant wave cost, fill planes and
+ * tail) predicts it at least 10 % faster, as for narrow 2D rows, small cubes
+ * and rows just wider than a tile.
  * Errors: DSM_EINVAL. */
 int dsm_set_tiling(dsm_sim* s, int variant, int planes);
 int dsm_tiling_variants(int dim);

@@ -341,17 +341,20 @@ int check_flag(dsm_sim* s) {
 
 }  // namespace
 
-// Default march of the 3D tile (variant 2): the longer of two plane counts
-// when its grid still fills every tile slot of the chip (slots = CUs x tiles
-// resident per CU) in whole rounds, the last at least 80 % busy; else the
-// shorter.  Longer marches re-read fewer fill planes.  Measured on MI355X:
-// FP32 (one tile per CU) 32 planes over 16, e.g. 128 x 256 x 128 at 17.5
-// GLUPS against 16.9 and 256 x 256 x 192 at 16.7 against 15.9; FP16 (two
-// tiles per CU) 16 planes over 8, e.g. 256 x 256 x 192 at 24.2 against 22.9;
-// 128^3 has too few tiles for the longer march in either storage.
-int default_planes_3d(const Geom& g, int slots, int longer, int shorter) {
+// Default march of the default tile (3D variant 2, 2D variant 0): the longer
+// of two plane counts when its grid still fills every tile slot of the chip
+// (slots = CUs x tiles resident per CU) in whole rounds, the last at least
+// 80 % busy; else the shorter.  Longer marches re-read fewer fill planes.
+// Measured on MI355X: 3D FP32 (one tile per CU) 32 planes over 16, e.g.
+// 128 x 256 x 128 at 17.5 GLUPS against 16.9 and 256 x 256 x 192 at 16.7
+// against 15.9; FP16 (two tiles per CU) 16 planes over 8, e.g. 256 x 256 x
+// 192 at 24.2 against 22.9; 128^3 has too few tiles for the longer march in
+// either storage.  2D (four 256-column tiles per CU) 16 rows over 8: rows of
+// 1000 columns keep 16, narrower ones gain from 8, e.g. D2Q9 200 x 4096 at
+// 25.1 GLUPS against 23.4 (FP16 30.9 against 24.4).
+int default_planes(const Geom& g, int dim, int slots, int longer, int shorter) {
     int tx = 0, ty = 0;
-    fused_tile_shape(3, 2, &tx, &ty);
+    fused_tile_shape(dim, dim == 3 ? 2 : 0, &tx, &ty);
     const long long tiles = (long long)((g.X + tx - 1) / tx) * ((g.Y + ty - 1) / ty);
     const long long n = tiles * ((g.Z + longer - 1) / longer);
     const long long rounds = (n + slots - 1) / slots;
@@ -450,10 +453,15 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 0;
-    if (p->dim == 3 && cus > 0)
-        s->tile_planes = s->half ? default_planes_3d(s->geom, 2 * cus, 16, 8)
-                                 : default_planes_3d(s->geom, cus, 32, 16);
-    if (cus > 0) default_tiling_by_model(s, cus);
+    if (cus > 0) {
+        if (p->dim == 3)
+            s->tile_planes = s->half ? default_planes(s->geom, 3, 2 * cus, 16, 8)
+                                     : default_planes(s->geom, 3, cus, 32, 16);
+        else
+            s->tile_planes = default_planes(
+                s->geom, 2, cus * fused_blocks_per_cu(2, 0, s->half, make_phys(s, 2).contrast), 16, 8);
+        default_tiling_by_model(s, cus);
+    }
     auto cleanup = [&](int rc) {
         delete s;
         return rc;
