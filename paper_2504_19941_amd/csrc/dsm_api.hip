@@ -341,24 +341,38 @@ int check_flag(dsm_sim* s) {
 
 }  // namespace
 
-// Default march of the default tile (3D variant 2, 2D variant 0): the longer
-// of two plane counts when its grid still fills every tile slot of the chip
-// (slots = CUs x tiles resident per CU) in whole rounds, the last at least
-// 80 % busy; else the shorter.  Longer marches re-read fewer fill planes.
-// Measured on MI355X: 3D FP32 (one tile per CU) 32 planes over 16, e.g.
-// 128 x 256 x 128 at 17.5 GLUPS against 16.9 and 256 x 256 x 192 at 16.7
-// against 15.9; FP16 (two tiles per CU) 16 planes over 8, e.g. 256 x 256 x
-// 192 at 24.2 against 22.9; 128^3 has too few tiles for the longer march in
-// either storage.  2D (four 256-column tiles per CU) 16 rows over 8: rows of
-// 1000 columns keep 16, narrower ones gain from 8, e.g. D2Q9 200 x 4096 at
-// 25.1 GLUPS against 23.4 (FP16 30.9 against 24.4).
-int default_planes(const Geom& g, int dim, int slots, int longer, int shorter) {
+// Default march of the default tile (3D variant 2, 2D variant 0), for a chip
+// of `slots` tile slots (CUs x tiles resident per CU).
+//
+// 3D: of 8, 16 and 32 planes, the march that takes the fewest whole rounds of
+// tiles times planes, each march's two fill planes counted as 0.36 of a plane
+// (ties go to the longer march, which re-reads fewer fill planes).  Measured
+// on MI355X: 128 x 256 x 128 FP32 at 17.5 GLUPS with 32 planes against 16.9
+// with 16; 256 x 256 x 192 FP16 at 24.2 with 16 against 22.9 with 8; 80^3
+// FP32 at 9.8 with 8 against 6.5 with 16; 128^3 keeps 16 (FP32) and 8 (FP16).
+//
+// 2D: 16 rows when the grid fills every slot in whole rounds, the last at
+// least 80 % busy, else 8: rows of 1000 columns keep 16, narrower ones gain
+// from 8, e.g. D2Q9 200 x 4096 at 25.1 GLUPS against 23.4 (FP16 30.9
+// against 24.4).
+int default_planes(const Geom& g, int dim, int slots) {
     int tx = 0, ty = 0;
     fused_tile_shape(dim, dim == 3 ? 2 : 0, &tx, &ty);
     const long long tiles = (long long)((g.X + tx - 1) / tx) * ((g.Y + ty - 1) / ty);
-    const long long n = tiles * ((g.Z + longer - 1) / longer);
-    const long long rounds = (n + slots - 1) / slots;
-    return slots > 0 && n >= slots && (double)n >= 0.8 * (double)(rounds * slots) ? longer : shorter;
+    if (slots < 1) return 16;
+    if (dim == 2) {
+        const long long n = tiles * ((g.Z + 15) / 16);
+        const long long rounds = (n + slots - 1) / slots;
+        return n >= slots && (double)n >= 0.8 * (double)(rounds * slots) ? 16 : 8;
+    }
+    double best = 0.0;
+    int planes = 16;
+    for (int p : {32, 16, 8}) {
+        const long long n = tiles * ((g.Z + p - 1) / p);
+        const double t = (double)((n + slots - 1) / slots) * ((p < g.Z ? p : g.Z) + 0.72);
+        if (p == 32 || t < best - 1e-9) best = t, planes = p;
+    }
+    return planes;
 }
 
 // Tilings of lattices unlike the measured ones above (narrow 2D rows, small
@@ -454,12 +468,8 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 0;
     if (cus > 0) {
-        if (p->dim == 3)
-            s->tile_planes = s->half ? default_planes(s->geom, 3, 2 * cus, 16, 8)
-                                     : default_planes(s->geom, 3, cus, 32, 16);
-        else
-            s->tile_planes = default_planes(
-                s->geom, 2, cus * fused_blocks_per_cu(2, 0, s->half, make_phys(s, 2).contrast), 16, 8);
+        const int slots = cus * fused_blocks_per_cu(p->dim, s->tile_variant, s->half, make_phys(s, 2).contrast);
+        s->tile_planes = default_planes(s->geom, p->dim, slots);
         default_tiling_by_model(s, cus);
     }
     auto cleanup = [&](int rc) {
