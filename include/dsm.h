@@ -210,6 +210,10 @@ long long dsm_step_count(const dsm_sim* s);
  * and rows just wider than a tile.
  * Errors: DSM_EINVAL. */
 int dsm_set_tiling(dsm_sim* s, int variant, int planes);
+/* The launch shape in use (the default chosen by dsm_create, or the last
+ * dsm_set_tiling): *variant and *planes as in dsm_set_tiling.  Either pointer
+ * may be NULL.  Errors: DSM_EINVAL (s is NULL). */
+int dsm_get_tiling(const dsm_sim* s, int* variant, int* planes);
 int dsm_tiling_variants(int dim);
 
 /* Releases the host handle (the device buffer stays the caller's). */

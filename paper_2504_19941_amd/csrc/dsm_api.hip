@@ -818,6 +818,13 @@ int dsm_set_tiling(dsm_sim* s, int variant, int planes) {
     return DSM_OK;
 }
 
+int dsm_get_tiling(const dsm_sim* s, int* variant, int* planes) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (variant) *variant = s->tile_variant;
+    if (planes) *planes = s->tile_planes;
+    return DSM_OK;
+}
+
 int dsm_tiling_variants(int dim) { return (dim == 2 || dim == 3) ? fused_tile_variants(dim) : 0; }
 
 int dsm_destroy(dsm_sim* s) {

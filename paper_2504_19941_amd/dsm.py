@@ -27,7 +27,7 @@ EXPORTED = [
     "dsm_set_gravity", "dsm_step", "dsm_step_timed", "dsm_free_energy", "dsm_mass", "dsm_fields",
     "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
     "dsm_state_bytes", "dsm_get_state", "dsm_set_state", "dsm_step_count", "dsm_set_tiling",
-    "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
+    "dsm_get_tiling", "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
     "dsm_batch_required_bytes", "dsm_batch_create", "dsm_batch_set_schedule", "dsm_batch_get_schedule",
     "dsm_batch_tune", "dsm_batch_step", "dsm_batch_step_timed", "dsm_batch_size", "dsm_batch_items",
     "dsm_batch_destroy",
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.dsm_step_count.argtypes = [vp]
     lib.dsm_step_count.restype = ctypes.c_longlong
     lib.dsm_set_tiling.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.dsm_get_tiling.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.dsm_tiling_variants.argtypes = [ctypes.c_int]
     lib.dsm_destroy.argtypes = [vp]
     lib.dsm_last_error.argtypes = []
@@ -266,6 +267,12 @@ def dsm_set_tiling(h, variant, planes):
     _check(load().dsm_set_tiling(h, int(variant), int(planes)), "dsm_set_tiling")
 
 
+def dsm_get_tiling(h):
+    v, p = ctypes.c_int(0), ctypes.c_int(0)
+    _check(load().dsm_get_tiling(h, ctypes.byref(v), ctypes.byref(p)), "dsm_get_tiling")
+    return v.value, p.value
+
+
 def dsm_tiling_variants(dim) -> int:
     return int(load().dsm_tiling_variants(int(dim)))
 
@@ -429,6 +436,10 @@ class Simulation:
 
     def set_tiling(self, variant, planes):
         dsm_set_tiling(self.handle, variant, planes)
+
+    def tiling(self):
+        """(variant, planes) of the fused step's launch shape in use."""
+        return dsm_get_tiling(self.handle)
 
     @property
     def steps(self) -> int:

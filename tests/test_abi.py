@@ -105,6 +105,7 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.dsm_free_energy(None, None, None) == dsm.DSM_EINVAL
     assert lib.dsm_tiling_variants(3) >= 1
     assert lib.dsm_tiling_variants(5) == 0
+    assert lib.dsm_get_tiling(None, None, None) == dsm.DSM_EINVAL
 
 
 def test_storage_modes_size_the_buffer(lib):

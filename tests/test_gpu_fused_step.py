@@ -86,6 +86,30 @@ def test_full_size_lattice_in_bench_configuration(gpu):
     assert report("mirror y", C2g, C2g[:, idx]) < 1e-6
 
 
+def test_default_tiling_and_its_readback(gpu):
+    """dsm_get_tiling reports the launch shape in use: the default dsm_create
+    chose, then whatever dsm_set_tiling set.  On a 256-CU MI355X the defaults
+    of the benchmark-type lattices are the measured best ones: 128x4 tiles
+    marching 16 planes for the 128^3 FP32 lattice and 8 with FP16 storage;
+    8 planes for an 80^3 FP32 lattice, too small to fill the chip with 16;
+    64-column tiles with 8-row marches for a D2Q9 lattice 300 columns wide."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    cases = [(3, (128, 128, 128), dsm.DSM_STORAGE_FP32, (2, 16)),
+             (3, (128, 128, 128), dsm.DSM_STORAGE_FP16, (2, 8)),
+             (3, (80, 80, 80), dsm.DSM_STORAGE_FP32, (2, 8)),
+             (2, (300, 8192), dsm.DSM_STORAGE_FP32, (2, 8))]
+    for dim, shape, storage, expect in cases:
+        sim = dsm.Simulation(dim, shape, KAPPA, storage=storage)
+        variant, planes = sim.tiling()
+        assert 0 <= variant < dsm.dsm_tiling_variants(dim) and planes in (8, 16, 32)
+        if cus == 256:
+            assert (variant, planes) == expect, (shape, storage, (variant, planes))
+        sim.set_tiling(0, 12)
+        assert sim.tiling() == (0, 12)
+        sim.close()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_launch_shape_does_not_change_results(gpu, dim):
     """Every tile variant and march length computes bit-identical states."""
