@@ -172,7 +172,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, l
 //
 // Occupancy.  The 3D tile holds the pulled g of its lead plane for one
 // iteration, until that plane's collision; in registers that brings it to
-// about 150 VGPRs (212 when pipelined), 2-3 waves per SIMD, one 8-wave tile
+// about 150 VGPRs (about 205 when pipelined), 2-3 waves per SIMD, one 8-wave tile
 // per CU.  With FP16 elements the 3D tile holds them instead as their raw
 // bits in a two-slot LDS buffer of per-thread cells (exact, 2 bytes each), and
 // the 3D FP16 kernels request 4 waves per SIMD, so two tiles share a CU: the FP16
