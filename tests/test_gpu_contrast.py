@@ -151,7 +151,8 @@ def test_two_layer_channel_flow(gpu, tau2, tau3, rho, tol):
     orc.close()
 
 
-def test_batch_with_contrast_members_matches_single_runs(gpu):
+@pytest.mark.parametrize("storage", [dsm.DSM_STORAGE_FP32, dsm.DSM_STORAGE_FP16])
+def test_batch_with_contrast_members_matches_single_runs(gpu, storage):
     specs = [(2, (100, 37), None), (2, (64, 32), (RHO, TAU3)), (3, (40, 21, 35), (RHO, TAU3)),
              (3, (33, 9, 12), None), (2, (129, 70), ((1.0, 1.0), 0.6))]
 
@@ -160,7 +161,7 @@ def test_batch_with_contrast_members_matches_single_runs(gpu):
         for k, (dim, shape, con) in enumerate(specs):
             mask, C1, C2 = wall_and_particle(dim, shape, seed=700 + k)
             kw = {} if con is None else dict(rho=con[0], tau_gas=con[1])
-            s = dsm.Simulation(dim, shape, KAPPA, gravity=(1e-5, 0.0, 0.0), **kw)
+            s = dsm.Simulation(dim, shape, KAPPA, gravity=(1e-5, 0.0, 0.0), storage=storage, **kw)
             s.set_solid_field(f32(W.flat(C1)))
             s.set_liquid(f32(W.flat(C2)))
             s.step(1)
