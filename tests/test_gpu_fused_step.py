@@ -33,7 +33,8 @@ def report(name, a, b):
 
 
 # shapes spanning several workgroup tiles with ragged tails on every axis
-# (3D tiles: 128 x 4 columns by 16 planes; 2D: 256 columns by 16 rows)
+# (the default 3D tile is 128 x 4 columns, the 2D tile 256 columns; marches of
+# 8-32 planes)
 SHAPES_1000 = [(2, (300, 37)), (3, (40, 21, 35)), (3, (130, 9, 18))]
 
 
