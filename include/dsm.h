@@ -117,29 +117,47 @@ size_t dsm_required_bytes(const dsm_params* p);
 int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t dev_bytes,
                void* stream, dsm_sim** out);
 
-/* Solid stage (Sec. II.B): n_steps lattice Boltzmann steps of the
- * solid-relaxation functional with confining strength beta and range
- * penalty Omega, relaxation times tau_s and tau_g = 1/2 + 3 mobility_s, every
- * node fluid, no body force.  flags: DSM_SOLID_RESET restarts from
- * C1 = 1[S] (otherwise the solid stage continues from its live state, so a
- * schedule can change beta and Omega between calls); DSM_SOLID_REMASK
- * replaces S by {C1 > 1/2} after the run (the two-step initialisation for
- * sharp corners).  On return C1 is frozen to the relaxed field; a liquid must
- * then be set with dsm_set_liquid.  Errors: DSM_EINVAL, DSM_EDEVICE. */
+/* Solid stage (Sec. II.B, the solid-relaxation functional "Free Energy1"
+ * with the confining potential of Sec. II.A): n_steps lattice Boltzmann
+ * steps with confining strength beta and range penalty Omega, relaxation
+ * times tau_s and tau_g = 1/2 + 3 mobility_s, every node fluid, no body
+ * force.  flags: DSM_SOLID_RESET restarts from C1 = 1[S] (otherwise the
+ * solid stage continues from its live state, so a schedule can change beta
+ * and Omega between calls); DSM_SOLID_REMASK replaces S by {C1 > 1/2} after
+ * the run (the two-step initialisation for sharp corners of Sec. II.B).  On
+ * return C1 is frozen to the relaxed field and the cut-link table of the
+ * fluid stage is rebuilt from it; a liquid must then be set with
+ * dsm_set_liquid.  Any stability flag of an earlier run is cleared first.
+ * Errors: DSM_EINVAL, DSM_EUNSTABLE (non-finite values during the run),
+ * DSM_EDEVICE.  After an error the handle holds no usable solid: the cut
+ * links are dropped and dsm_set_liquid returns DSM_ESTATE until a solid
+ * stage or dsm_set_solid_field succeeds. */
 int dsm_init_solid(dsm_sim* s, int n_steps, double beta, double omega, double tau_s,
                    double mobility_s, int flags);
 
-/* Alternative to the solid stage: a given diffuse solid C1 (host, N values;
- * stored in FP32).  Invalidates any liquid state.  Errors: DSM_EINVAL,
- * DSM_EDEVICE. */
+/* Alternative to the solid stage: a given diffuse solid C1 (host, N values
+ * in node order; stored in FP32), e.g. the tanh profile of a signed distance
+ * that the equilibrium interface of Sec. II.A takes (eqn:tanh).  Nodes with
+ * C1 > 1/2 become solid nodes of the fluid stage (Sec. II.B) and the cut
+ * links of interpolated bounce-back are rebuilt.  Invalidates any liquid
+ * state.  Errors: DSM_EINVAL (NULL argument, or more cut links than the
+ * table holds), DSM_EDEVICE. */
 int dsm_set_solid_field(dsm_sim* s, const double* C1);
 
-/* Liquid initial condition at t = 0 (host, N values): f = 0 and
- * g = g_eq(C2, mu(C2), u = 0) at every node.  Errors: DSM_EINVAL,
+/* Liquid initial condition at t = 0 of the fluid stage (Sec. II.B; host,
+ * N values of C2 in node order, with C3 = 1 - C1 - C2 as in Sec. II.A):
+ * f = 0 and g = g_eq(C2, mu(C2), u = 0) at every node, with the equilibrium
+ * g_eq and the chemical potential mu of the frozen-solid functional of
+ * Sec. II.B.  Resets the step count and the stability flag.  Errors:
+ * DSM_EINVAL, DSM_ESTATE (the last solid stage or solid field failed),
  * DSM_EDEVICE. */
 int dsm_set_liquid(dsm_sim* s, const double* C2);
 
-/* Replaces the body-force density (between steps, e.g. for ramps). */
+/* Replaces the body-force density g of the force F_g = C2 g on the liquid
+ * (host, 3 values; the gravitational energy of Sec. III.B and the force on
+ * the droplet of Sec. IV.B), between steps, e.g. for a ramp.  Takes effect
+ * at the next step; no device work.  Errors: DSM_EINVAL (NULL, non-finite,
+ * or g[2] != 0 when dim == 2). */
 int dsm_set_gravity(dsm_sim* s, const double g[3]);
 
 /* n fluid-stage time steps (Sec. II.B, frozen solid), stream-ordered.
@@ -162,13 +180,41 @@ int dsm_step_timed(dsm_sim* s, int n, double* step_ms, double* links_ms);
  * may be NULL.  Errors: DSM_ESTATE, DSM_EDEVICE. */
 int dsm_free_energy(dsm_sim* s, double* F, double* E_kin);
 
-/* Total amounts sum_x C1, C2, C3 (FP64 reduction; synchronises). */
+/* Total amounts m[k] = sum_x C_{k+1} (FP64 reduction; synchronises).  The
+ * scheme conserves each component's amount (Sec. II.B: the zeroth moment of
+ * g is C and both the collision and the streaming preserve it); the evolving
+ * component is summed from the stored populations themselves, so a drift
+ * measures the stored state.  Errors: DSM_EINVAL, DSM_ESTATE, DSM_EDEVICE. */
 int dsm_mass(dsm_sim* s, double m[3]);
 
-/* Macroscopic fields of the current state (synchronises): C1, C2, C3, the
- * velocity u (dim planes) and the pressure P = p~ / 3, where p~ is the zeroth
- * moment of f.  Any pointer may be NULL.  Errors: DSM_ESTATE, DSM_EDEVICE. */
+/* Macroscopic fields of the current state (synchronises; host arrays of N
+ * doubles in node order): C1, C2, C3 = 1 - C1 - C2 (Sec. II.A), the velocity
+ * u (dim planes; rho u = sum_i c_i f_i + F/2, Sec. II.B) and the pressure
+ * P = p~ / 3, where p~ = sum_i f_i + u . grad(rho) / 2 is the zeroth moment
+ * of f (Sec. II.B).  Solid nodes report u = 0 and P = 0.  Any pointer may be
+ * NULL.  Errors: DSM_EINVAL, DSM_ESTATE, DSM_EDEVICE. */
 int dsm_fields(dsm_sim* s, double* C1, double* C2, double* C3, double* u, double* p);
+
+/* Global diagnostics of the current state, from one FP64 reduction over
+ * every node (synchronises): the amounts of dsm_mass, the free energy and
+ * kinetic energy of dsm_free_energy, the largest speed max_x |u(x)| (u as in
+ * dsm_fields, which measures how far a run is from a static equilibrium),
+ * and the number of nodes holding a non-finite C1, C2 or u. */
+typedef struct {
+    double mass[3];
+    double free_energy;
+    double kinetic_energy;
+    double max_speed;
+    double nonfinite_nodes;
+} dsm_diag;
+int dsm_diagnostics(dsm_sim* s, dsm_diag* out);
+
+/* The solid region S the confining potential currently holds the solid to
+ * (Sec. II.A; host, N bytes in node order, 1 in S): the mask given to
+ * dsm_create, or {C1 > 1/2} after a solid stage run with DSM_SOLID_REMASK
+ * (the redefinition of the solid locations in the two-step initialisation of
+ * Sec. II.B).  Synchronises.  Errors: DSM_EINVAL, DSM_EDEVICE. */
+int dsm_solid_region(dsm_sim* s, uint8_t* mask);
 
 /* Chemical potential mu of the current state (host, N values). */
 int dsm_chemical_potential(dsm_sim* s, double* mu);

@@ -205,6 +205,8 @@ int dsmo_create(const dsmo_params* p, const unsigned char* mask, dsmo_sim** out)
     if (p->dim == 2 && p->nz != 1) return DSMO_EINVAL;
     if (!(p->tau > 0.5) || !(p->mobility > 0.0) || !(p->alpha > 0.0)) return DSMO_EINVAL;
     if (!(p->rho_liquid > 0.0) || !(p->rho_gas > 0.0) || !(p->tau_gas > 0.5)) return DSMO_EINVAL;
+    if (p->force_reading != DSMO_FORCE_POTENTIAL && p->force_reading != DSMO_FORCE_AS_TYPESET)
+        return DSMO_EINVAL;
     for (int k = 0; k < 3; ++k)
         if (!(p->kappa[k] >= 0.0)) return DSMO_EINVAL;
 
@@ -344,24 +346,30 @@ static void stage_chemical_potential(dsmo_sim* s) {
  * The surface-tension force is taken in the potential form F_s = mu grad phi,
  * the form that the paper's velocity moment carries.  The paper also states
  * F_s = -phi grad mu; the two differ by grad(phi mu), which the pressure of
- * the incompressible model absorbs, so they describe the same flow.  On the
- * lattice they do not behave alike: with -phi grad mu and isotropic central
- * differences a grid-scale (checkerboard) velocity mode grows without bound
- * at the paper's parameters (tau = 1, gamma = 2.5e-3) after some 10^5 steps,
- * while mu grad phi stays stable. */
+ * the incompressible model absorbs, so they describe the same flow and the
+ * same static equilibria.  The typeset form is kept behind force_reading so
+ * that the two can be compared. */
 static void stage_force(dsmo_sim* s) {
     long N = s->N;
     int body = s->stage == 2;
+    int typeset = s->p.force_reading == DSMO_FORCE_AS_TYPESET;
 #pragma omp parallel for num_threads(threads_of(s)) schedule(static)
     for (long n = 0; n < N; ++n) {
         double Fx = 0.0, Fy = 0.0, Fz = 0.0;
         if (!is_solid(s, n)) {
             double gp[3];
-            grad(s, s->phi, n, gp);
             double ph = s->phi[n], m = s->mu[n];
-            Fx = m * gp[0];
-            Fy = m * gp[1];
-            Fz = m * gp[2];
+            if (typeset) {
+                grad(s, s->mu, n, gp);
+                Fx = -ph * gp[0];
+                Fy = -ph * gp[1];
+                Fz = -ph * gp[2];
+            } else {
+                grad(s, s->phi, n, gp);
+                Fx = m * gp[0];
+                Fy = m * gp[1];
+                Fz = m * gp[2];
+            }
             if (body) {
                 Fx += ph * s->p.gravity[0];
                 Fy += ph * s->p.gravity[1];
@@ -507,6 +515,12 @@ static double link_q(const dsmo_sim* s, long n, int k) {
     if (q < 0.0) q = 0.0;
     if (q > 1.0) q = 1.0;
     return q;
+}
+
+int dsmo_get_mask(const dsmo_sim* s, unsigned char* mask) {
+    if (!s || !mask) return DSMO_EINVAL;
+    memcpy(mask, s->mask, (size_t)s->N);
+    return DSMO_OK;
 }
 
 double dsmo_link_q(dsmo_sim* s, long n, int k) {

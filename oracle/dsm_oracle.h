@@ -41,6 +41,12 @@ enum {
  *     show that they fail to confine the solid). */
 enum { DSMO_CONFINE_PURPOSE = 0, DSMO_CONFINE_AS_TYPESET = 1 };
 
+/* readings of the surface-tension force (Sec. II.B states F_s = -C grad mu
+ * and also writes the velocity moment with mu grad C):
+ * 0 = F_s = mu grad C, the potential form the velocity moment carries,
+ * 1 = F_s = -C grad mu as typeset (kept so that a test can compare them). */
+enum { DSMO_FORCE_POTENTIAL = 0, DSMO_FORCE_AS_TYPESET = 1 };
+
 /* init_solid flags */
 enum { DSMO_SOLID_RESET = 1, DSMO_SOLID_REMASK = 2 };
 
@@ -60,6 +66,7 @@ typedef struct {
     double rho_liquid;   /* rho_2 > 0 */
     double rho_gas;      /* rho_3 > 0 */
     double tau_gas;      /* tau_3 > 1/2 */
+    int force_reading;   /* DSMO_FORCE_* */
 } dsmo_params;
 
 typedef struct dsmo_sim dsmo_sim;
@@ -96,6 +103,10 @@ int  dsmo_set_populations(dsmo_sim* s, const double* f, const double* g);
 /* Sets the state to stream(f*, g*): the given arrays are post-collision
  * populations, and the oracle performs its own streaming step on them. */
 int  dsmo_set_postcollision(dsmo_sim* s, const double* fs, const double* gs);
+
+/* The solid region S currently held (N bytes, 1 in S); after a solid stage
+ * run with REMASK it is {C1 > 1/2}. */
+int  dsmo_get_mask(const dsmo_sim* s, unsigned char* mask);
 
 /* Wall fraction q of the link leaving fluid node n along direction k. */
 double dsmo_link_q(dsmo_sim* s, long n, int k);

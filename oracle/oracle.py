@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(HERE, "libdsm_oracle.so")
 
 CONFINE_PURPOSE = 0
 CONFINE_AS_TYPESET = 1
+FORCE_POTENTIAL = 0
+FORCE_AS_TYPESET = 1
 SOLID_RESET = 1
 SOLID_REMASK = 2
 
@@ -26,6 +28,7 @@ class _Params(ctypes.Structure):
         ("mobility", ctypes.c_double), ("gravity", ctypes.c_double * 3),
         ("confine_reading", ctypes.c_int), ("threads", ctypes.c_int),
         ("rho_liquid", ctypes.c_double), ("rho_gas", ctypes.c_double), ("tau_gas", ctypes.c_double),
+        ("force_reading", ctypes.c_int),
     ]
 
 
@@ -57,6 +60,7 @@ def load():
     lib.dsmo_get_populations.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.dsmo_set_populations.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.dsmo_set_postcollision.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.dsmo_get_mask.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.dsmo_link_q.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_int]
     lib.dsmo_link_q.restype = ctypes.c_double
     lib.dsmo_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]
@@ -117,9 +121,12 @@ class Oracle:
 
     def __init__(self, dim, shape, kappa, alpha=1.0, tau=1.0, mobility=0.1,
                  gravity=(0.0, 0.0, 0.0), mask=None, threads=1,
-                 confine_reading=CONFINE_PURPOSE, rho=(1.0, 1.0), tau_gas=None):
+                 confine_reading=CONFINE_PURPOSE, rho=(1.0, 1.0), tau_gas=None,
+                 force_reading=FORCE_POTENTIAL):
         """rho = (rho_2, rho_3) of liquid and gas; tau_gas = tau_3 (default:
-        tau, i.e. no viscosity contrast)."""
+        tau, i.e. no viscosity contrast); force_reading selects the form of
+        the surface-tension force (FORCE_POTENTIAL: mu grad C, the form used
+        throughout; FORCE_AS_TYPESET: -C grad mu)."""
         lib = load()
         nx, ny = shape[0], shape[1]
         nz = shape[2] if dim == 3 else 1
@@ -133,6 +140,7 @@ class Oracle:
         p.confine_reading, p.threads = int(confine_reading), int(threads)
         p.rho_liquid, p.rho_gas = float(rho[0]), float(rho[1])
         p.tau_gas = float(tau if tau_gas is None else tau_gas)
+        p.force_reading = int(force_reading)
         h = ctypes.c_void_p()
         m = None
         if mask is not None:
@@ -209,6 +217,11 @@ class Oracle:
     def set_postcollision(self, fs, gs):
         fs, gs = _f64(fs), _f64(gs)
         _check(self._lib.dsmo_set_postcollision(self._h, _ptr(fs), _ptr(gs)), "set_postcollision")
+
+    def mask(self):
+        m = np.zeros(self.N, dtype=np.uint8)
+        _check(self._lib.dsmo_get_mask(self._h, m.ctypes.data_as(ctypes.c_void_p)), "get_mask")
+        return m
 
     def link_q(self, node, k):
         return self._lib.dsmo_link_q(self._h, int(node), int(k))

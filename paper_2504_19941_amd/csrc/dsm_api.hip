@@ -504,6 +504,11 @@ int dsm_init_solid(dsm_sim* s, int n_steps, double beta, double omega, double ta
     s->omega = omega;
     s->tau_s = tau_s;
     s->taug_s = 0.5 + 3.0 * mobility_s;
+    // The cut links of the previous C1 must not outlive it, and a stability
+    // flag left by an earlier run must not be taken for this run's.
+    s->nlinks = 0;
+    s->solid_failed = 1;
+    HIP_TRY(hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream));
     if ((flags & DSM_SOLID_RESET) || s->stage != 1) {
         s->stage = 1;
         HIP_TRY(launch_c1_from_mask(s->d.mask, s->d.phi, s->N, s->stream));
@@ -520,22 +525,26 @@ int dsm_init_solid(dsm_sim* s, int n_steps, double beta, double omega, double ta
     HIP_TRY(hipStreamSynchronize(s->stream));
     int rc = check_flag(s);
     if (!rc) rc = build_links(s);
+    if (!rc) s->solid_failed = 0;
     return rc;
 }
 
 int dsm_set_solid_field(dsm_sim* s, const double* C1) {
     if (!s || !C1) return fail(DSM_EINVAL, "NULL argument");
+    s->nlinks = 0;
+    s->solid_failed = 1;
     int rc = upload_field(s, C1, s->d.c1);
     if (rc) return rc;
     s->stage = 0;
-    return build_links(s);
+    rc = build_links(s);
+    if (!rc) s->solid_failed = 0;
+    return rc;
 }
 
 int dsm_set_liquid(dsm_sim* s, const double* C2) {
     if (!s || !C2) return fail(DSM_EINVAL, "NULL argument");
-    if (s->stage == 1) {
-        // leaving the solid stage: C1 already frozen by dsm_init_solid
-    }
+    if (s->solid_failed)
+        return fail(DSM_ESTATE, "the last solid stage or solid field failed; set the solid again first");
     int rc = upload_field(s, C2, s->d.phi);
     if (rc) return rc;
     s->stage = 2;
@@ -645,6 +654,29 @@ int dsm_mass(dsm_sim* s, double m[3]) {
     m[0] = r[RED_C1];
     m[1] = r[RED_C2];
     m[2] = r[RED_C3];
+    return DSM_OK;
+}
+
+int dsm_solid_region(dsm_sim* s, uint8_t* mask) {
+    if (!s || !mask) return fail(DSM_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(mask, s->d.mask, (size_t)s->N, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return DSM_OK;
+}
+
+int dsm_diagnostics(dsm_sim* s, dsm_diag* out) {
+    if (!s || !out) return fail(DSM_EINVAL, "NULL argument");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    double r[RED_SLOTS];
+    int rc = reduce(s, r);
+    if (rc) return rc;
+    out->mass[0] = r[RED_C1];
+    out->mass[1] = r[RED_C2];
+    out->mass[2] = r[RED_C3];
+    out->free_energy = r[RED_FREE];
+    out->kinetic_energy = r[RED_EKIN];
+    out->max_speed = r[RED_UMAX];
+    out->nonfinite_nodes = r[RED_NONFINITE];
     return DSM_OK;
 }
 
@@ -803,7 +835,10 @@ int dsm_set_state(dsm_sim* s, const void* host, size_t bytes) {
     s->omega = h.omega;
     s->tau_s = h.tau_s;
     s->taug_s = h.taug_s;
-    return build_links(s);
+    s->solid_failed = 1;
+    int rc = build_links(s);
+    if (!rc) s->solid_failed = 0;
+    return rc;
 }
 
 long long dsm_step_count(const dsm_sim* s) { return s ? s->steps : -1; }

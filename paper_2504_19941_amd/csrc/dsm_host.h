@@ -21,6 +21,7 @@ struct dsm_sim {
     long long steps;
     double beta, omega, tau_s, taug_s;
     int nlinks;        // boundary nodes with cut links (fluid stage)
+    int solid_failed;  // the last solid stage failed: C1 and its cut links are unusable
     int tile_variant;  // workgroup tile of the fused step
     int tile_planes;   // planes marched per workgroup
     int half;      // populations stored in FP16 (value * kHalfScale)

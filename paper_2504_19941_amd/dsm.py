@@ -24,7 +24,8 @@ DSM_STORAGE_FP32, DSM_STORAGE_FP16 = 0, 1
 
 EXPORTED = [
     "dsm_required_bytes", "dsm_create", "dsm_init_solid", "dsm_set_solid_field", "dsm_set_liquid",
-    "dsm_set_gravity", "dsm_step", "dsm_step_timed", "dsm_free_energy", "dsm_mass", "dsm_fields",
+    "dsm_set_gravity", "dsm_step", "dsm_step_timed", "dsm_free_energy", "dsm_mass", "dsm_diagnostics",
+    "dsm_solid_region", "dsm_fields",
     "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
     "dsm_state_bytes", "dsm_get_state", "dsm_set_state", "dsm_step_count", "dsm_set_tiling",
     "dsm_get_tiling", "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
@@ -48,6 +49,12 @@ class dsm_params(ctypes.Structure):
 
 class dsm_batch_schedule(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int), ("planes", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
+
+
+class dsm_diag(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double * 3), ("free_energy", ctypes.c_double),
+                ("kinetic_energy", ctypes.c_double), ("max_speed", ctypes.c_double),
+                ("nonfinite_nodes", ctypes.c_double)]
 
 
 class DsmError(RuntimeError):
@@ -87,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.dsm_step_timed.argtypes = [vp, ctypes.c_int, _dp, _dp]
     lib.dsm_free_energy.argtypes = [vp, _dp, _dp]
     lib.dsm_mass.argtypes = [vp, _dp]
+    lib.dsm_diagnostics.argtypes = [vp, ctypes.POINTER(dsm_diag)]
+    lib.dsm_solid_region.argtypes = [vp, vp]
     lib.dsm_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
     lib.dsm_chemical_potential.argtypes = [vp, _dp]
     lib.dsm_get_populations.argtypes = [vp, _dp, _dp]
@@ -210,6 +219,19 @@ def dsm_free_energy(h):
 def dsm_mass(h):
     m = np.zeros(3)
     _check(load().dsm_mass(h, _p(m)), "dsm_mass")
+    return m
+
+
+def dsm_diagnostics(h):
+    d = dsm_diag()
+    _check(load().dsm_diagnostics(h, ctypes.byref(d)), "dsm_diagnostics")
+    return {"mass": np.array(d.mass[:]), "free_energy": d.free_energy, "kinetic_energy": d.kinetic_energy,
+            "max_speed": d.max_speed, "nonfinite_nodes": d.nonfinite_nodes}
+
+
+def dsm_solid_region(h, N):
+    m = np.zeros(N, dtype=np.uint8)
+    _check(load().dsm_solid_region(h, m.ctypes.data_as(ctypes.c_void_p)), "dsm_solid_region")
     return m
 
 
@@ -415,6 +437,12 @@ class Simulation:
 
     def fields(self):
         return dsm_fields(self.handle, self.N, self.dim)
+
+    def diagnostics(self):
+        return dsm_diagnostics(self.handle)
+
+    def solid_region(self):
+        return dsm_solid_region(self.handle, self.N)
 
     def chemical_potential(self):
         return dsm_chemical_potential(self.handle, self.N)

@@ -84,22 +84,30 @@ def test_steps_from_liquid(gpu, dim, kernel):
     Fo, Eo = orc.free_energy()
     assert abs(Fg - Fo) / abs(Fo) < 1e-5
     assert abs(Eg - Eo) <= 1e-3 * abs(Eo) + 1e-12
+    # the same FP64 reduction through dsm_diagnostics, with the largest speed
+    d = sim.diagnostics()
+    assert np.array_equal(d["mass"], m1)
+    assert d["free_energy"] == Fg and d["kinetic_energy"] == Eg
+    speed_o = float(np.sqrt((fo["u"] ** 2).sum(axis=0)).max())
+    print(f"  max speed: gpu {d['max_speed']:.6e}, oracle {speed_o:.6e}", flush=True)
+    assert abs(d["max_speed"] - speed_o) <= 1e-3 * speed_o
+    assert d["nonfinite_nodes"] == 0.0
 
 
 @pytest.mark.parametrize("storage,bar", [(dsm.DSM_STORAGE_FP32, 1e-5), (dsm.DSM_STORAGE_FP16, 2e-3)])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_solid_stage(gpu, dim, storage, bar):
     """Solid stage from the sharp mask (confinement and range penalty on),
-    then the frozen C1 against the oracle; with FP16 population storage to
-    the FP16 bar."""
+    1000 steps in two calls with different beta and Omega, then the frozen C1
+    against the oracle; with FP16 population storage to the FP16 bar."""
     shape = SHAPES[dim]
     mask, _, _ = wall_and_particle(dim, shape, seed=31)
     m = W.flat(mask)
     k = W.kappas_for_angle(90.0)
     sim, orc = pair(dim, shape, dsm.DSM_KERNEL_FUSED, kappa=k, mask=m, storage=storage)
     for s in (sim, orc):
-        s.init_solid(150, 1e-2, 1e-2, 1.0, 1.0 / 6.0, dsm.DSM_SOLID_RESET)
-        s.init_solid(50, 1e-3, 2e-4, 1.0, 1.0 / 6.0, 0)
+        s.init_solid(300, 1e-2, 1e-2, 1.0, 1.0 / 6.0, dsm.DSM_SOLID_RESET)
+        s.init_solid(700, 1e-3, 2e-4, 1.0, 1.0 / 6.0, 0)
     fg, fo = sim.fields(), orc.fields()
     assert report("C1", fg["C1"], fo["C1"]) < bar
 

@@ -2,10 +2,12 @@
 paper's liquid/gas viscosity contrast, particles at an interface; FP32 and
 FP16 storage) submitted while others run, admitted by
 footprint into one device arena, advanced together by the batched step, give
-exactly the result each gives alone."""
+exactly the result each gives alone; and served jobs of each kind and
+storage match the FP64 oracle run of the same job."""
 import numpy as np
 import pytest
 
+from oracle.oracle import Oracle
 from paper_2504_19941_amd import dsm
 from paper_2504_19941_amd import serve as S
 from paper_2504_19941_amd import workloads as W
@@ -85,3 +87,42 @@ def test_admission_by_footprint_queues_and_completes(gpu):
     adm = [j.admitted for j in jobs]
     assert adm == sorted(adm)
     check_alone(jobs)
+
+
+def test_served_jobs_match_the_oracle(gpu):
+    """A mix of eight jobs served together (300-600 steps each, quantum 50):
+    a capillary duct with the paper's capillary-filling viscosities
+    (tau_3 = 0.52 against tau_2 = 1) and a particle at an interface in FP32,
+    within 1e-5 of the oracle's C2 (and u within 1e-6); a duct and a particle
+    with FP16 storage within 2e-3."""
+    pairs = W.serve_jobs(8, seed=41, steps=(300, 600), small=True)
+    storage = {0: dsm.DSM_STORAGE_FP32, 2: dsm.DSM_STORAGE_FP32, 3: dsm.DSM_STORAGE_FP16,
+               5: dsm.DSM_STORAGE_FP16}
+    jobs = [S.Job(k, w, n, storage=storage.get(k, dsm.DSM_STORAGE_FP32)) for k, (w, n) in enumerate(pairs)]
+    srv = S.make_gpu_server(512 << 20, quantum=50)
+    for j in jobs:
+        srv.submit(j, 0.0)
+    rounds = 0
+    while srv.busy:
+        srv.step(float(rounds))
+        rounds += 1
+        assert rounds < 1000
+    checked = set()
+    for k, st in storage.items():
+        j = jobs[k]
+        w = j.workload
+        kind = "duct" if "channel" in w.name else "particle"
+        checked.add((kind, st))
+        orc = Oracle(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
+                     gravity=w.gravity, rho=w.rho, tau_gas=w.tau_gas, threads=16)
+        orc.set_solid_field(f32(W.flat(w.C1)))
+        orc.set_liquid(f32(W.flat(w.C2)))
+        orc.step(j.steps)
+        fo = orc.fields()
+        orc.close()
+        err = float(np.abs(j.result["C2"] - fo["C2"]).max())
+        bar = 1e-5 if st == dsm.DSM_STORAGE_FP32 else 2e-3
+        print(f"  job {k} {w.name} ({kind}, tau_gas {w.tau_gas}) storage {st}, {j.steps} steps: "
+              f"max |dC2| vs oracle {err:.2e} (bar {bar:g})", flush=True)
+        assert err < bar
+    assert checked == {("duct", 0), ("particle", 0), ("duct", 1), ("particle", 1)}

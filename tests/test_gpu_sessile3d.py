@@ -1,0 +1,100 @@
+"""The D3Q19 sessile-drop workload on the GPU against stored FP64 oracle runs
+(written by tests/golden/make_sessile3d_golden.py and
+tests/golden/make_bench_lattice_golden.py, which call only the oracle):
+
+* the contact angle of a 64^3 / R = 15 drop (the stated reduction of the
+  128^3 / R = 30 workload the oracle cannot run for tens of thousands of
+  steps) at 60, 90 and 120 degrees follows the oracle's within 0.5 degree
+  (FP32) and 1 degree (FP16 storage) at every stored record, with the
+  liquid amount conserved;
+* the full 128^3 lattice, in the launch configuration the benchmark times,
+  after 1000 steps: C2 within 1e-5 of the oracle at the stored nodes (FP32),
+  within 2e-3 with FP16 storage.
+
+Inputs are rounded to FP32 first, as in the stored runs."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2504_19941_amd import analysis as A
+from paper_2504_19941_amd import dsm
+from paper_2504_19941_amd import workloads as W
+
+from .conftest import f32
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"missing {path}")
+    return json.load(open(path))
+
+
+def report(name, a, b):
+    err = float(np.abs(np.asarray(a) - np.asarray(b)).max())
+    print(f"  {name}: max abs err {err:.3e}", flush=True)
+    return err
+
+
+@pytest.mark.parametrize("storage,bar", [(dsm.DSM_STORAGE_FP32, 0.5), (dsm.DSM_STORAGE_FP16, 1.0)])
+@pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
+def test_3d_contact_angle_follows_oracle(gpu, theta, storage, bar):
+    g = golden(f"sessile3d_d3q19_64cube_R15_theta{theta:g}.json")
+    w = W.config_3d_sessile(theta, n=64, radius=15.0)
+    assert list(w.kappa) == pytest.approx(g["kappa"], abs=0)
+    sim = dsm.Simulation(3, w.shape, w.kappa, tau=w.tau, mobility=w.mobility, storage=storage,
+                         reduce_every=2500)
+    sim.set_solid_field(f32(W.flat(w.C1)))
+    sim.set_liquid(f32(W.flat(w.C2)))
+    m0 = sim.mass()
+    assert abs(m0[1] - g["mass0"][1]) <= 1e-9 * g["mass0"][1]
+    done = 0
+    for rec in g["history"]:
+        sim.step(rec["step"] - done)
+        done = rec["step"]
+        fl = sim.fields()
+        th = A.contact_angle(W.unflat(fl["C1"], w.shape), W.unflat(fl["C2"], w.shape), 2, w.wall_level)
+        print(f"  theta {theta:g} storage {storage}: step {done}: gpu {th:.3f}, oracle {rec['theta']:.3f}",
+              flush=True)
+        assert abs(th - rec["theta"]) < bar
+    drift = abs(sim.mass()[1] - m0[1]) / m0[1]
+    print(f"  liquid mass drift after {done} steps: {drift:.1e}", flush=True)
+    assert drift < 1e-9
+    c = W.unflat(fl["C2"], w.shape)
+    lines = g["final_lines"]
+    axis = c[32, 32, :]
+    (key_x,) = [k for k in lines if k.startswith("line_x_z")]
+    line_x = c[:, 32, int(key_x[len("line_x_z"):])]
+    tol = 1e-4 if storage == dsm.DSM_STORAGE_FP32 else 2e-3
+    assert report(f"C2 on the drop axis after {done} steps", axis, lines["axis_z"]) < tol
+    assert report(f"C2 across the contact line after {done} steps", line_x, lines[key_x]) < tol
+
+
+@pytest.mark.parametrize("storage,bar_c,bar_u", [(dsm.DSM_STORAGE_FP32, 1e-5, 1e-6),
+                                                 (dsm.DSM_STORAGE_FP16, 2e-3, 1e-4)])
+def test_full_size_lattice_1000_steps_matches_oracle(gpu, storage, bar_c, bar_u):
+    """128^3, hemispherical drop R = 30 spreading towards 60 degrees, the
+    default tiling (the benchmark's launch shape), 1000 steps."""
+    g = golden("sessile3d_d3q19_128cube_R30_theta60_1000steps.json")
+    w = W.config_3d_sessile(60.0, n=128)
+    sim = dsm.Simulation(3, w.shape, w.kappa, tau=w.tau, mobility=w.mobility, storage=storage,
+                         reduce_every=250)
+    sim.set_solid_field(f32(W.flat(w.C1)))
+    sim.set_liquid(f32(W.flat(w.C2)))
+    print(f"  tiling {sim.tiling()}", flush=True)
+    sim.step(g["steps"])
+    fl = sim.fields()
+    idx = np.asarray(g["nodes"])
+    assert report("C2 at the stored nodes", fl["C2"][idx], g["C2"]) < bar_c
+    assert report("u at the stored nodes", fl["u"][:, idx], np.asarray(g["u"])) < bar_u
+    m = sim.mass()
+    assert abs(m[1] - g["mass0"][1]) / g["mass0"][1] < 1e-9
+    F, E = sim.free_energy()
+    print(f"  F gpu {F:.9e} oracle {g['F']:.9e}; E_kin gpu {E:.6e} oracle {g['Ekin']:.6e}", flush=True)
+    assert abs(F - g["F"]) <= 1e-5 * abs(g["F"])

@@ -1,0 +1,288 @@
+"""More pins of the FP64 oracle (no GPU): closed forms for the isotropic
+stencils, for interpolated bounce-back with the wall off the half-way
+position, for the two-step solid initialisation, and a comparison of the two
+forms of the surface-tension force the paper states.
+
+Each test names the passage it follows and the plausible slip it would
+catch."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle.mini_oracle import MiniOracle
+from paper_2504_19941_amd import analysis as A
+from paper_2504_19941_amd import workloads as W
+
+
+# --- stencils: exact action on a sine wave ----------------------------------
+#
+# Sec. II.B asks for second-order isotropic central differences; the readings
+# are G[a] = 3 sum_i w_i c_i a(x + c_i) and L[a] = 6 sum_i w_i (a(x + c_i) - a(x)).
+# Along a lattice axis, with k = 2 pi m / n, both lattices weigh the planes
+# x +- 1 by 1/6 in total, so exactly
+#   G_x[sin kx] = sin k cos kx,     L[sin kx] = 2 (cos k - 1) sin kx.
+# A wrong weight, a lost factor 3 or 6, or a sign slip changes these.
+
+def _axis_wave(dim, shape, axis, m, amp, base):
+    X = np.meshgrid(*[np.arange(n, dtype=float) for n in shape], indexing="ij")
+    k = 2.0 * math.pi * m / shape[axis]
+    return k, X[axis], base + amp * np.sin(k * X[axis])
+
+
+@pytest.mark.parametrize("dim,shape,axis", [(2, (24, 20), 0), (2, (24, 20), 1), (3, (12, 10, 14), 0),
+                                            (3, (12, 10, 14), 1), (3, (12, 10, 14), 2)])
+def test_laplacian_of_a_sine_wave(oracle_lib, dim, shape, axis):
+    """The fluid-stage mu = bulk(C) - alpha^2 (k2 + k3) L[C2] when C1 = 0, so
+    changing alpha from 1 to 2 at fixed fields changes mu by exactly
+    -3 (k2 + k3) L[C2]: L is read off the oracle's own mu without retyping
+    the bulk polynomial."""
+    k, x, C2 = _axis_wave(dim, shape, axis, 2, 0.2, 0.4)
+    N = int(np.prod(shape))
+    kap = (0.0, 0.006, 0.004)
+    mus = []
+    for alpha in (1.0, 2.0):
+        o = O.Oracle(dim, shape, kap, alpha=alpha)
+        o.set_solid_field(np.zeros(N))
+        o.set_liquid(W.flat(C2))
+        mus.append(o.chemical_potential())
+    lap = (mus[0] - mus[1]) / (3.0 * (kap[1] + kap[2]))
+    exact = 2.0 * (math.cos(k) - 1.0) * 0.2 * np.sin(k * x)
+    assert np.abs(lap - W.flat(exact)).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim,shape,axis", [(2, (24, 20), 1), (3, (12, 10, 14), 2)])
+def test_laplacian_of_the_solid_field(oracle_lib, dim, shape, axis):
+    """The same for the solid's term -alpha^2 k3 L[C1] of the fluid-stage mu
+    (C1 below 1/2 everywhere, so no node is solid)."""
+    k, x, C1 = _axis_wave(dim, shape, axis, 1, 0.15, 0.25)
+    N = int(np.prod(shape))
+    kap = (0.01, 0.0, 0.005)
+    mus = []
+    for alpha in (1.0, 2.0):
+        o = O.Oracle(dim, shape, kap, alpha=alpha)
+        o.set_solid_field(W.flat(C1))
+        o.set_liquid(np.full(N, 0.2))
+        mus.append(o.chemical_potential())
+    lap = (mus[0] - mus[1]) / (3.0 * kap[2])
+    exact = 2.0 * (math.cos(k) - 1.0) * 0.15 * np.sin(k * x)
+    assert np.abs(lap - W.flat(exact)).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim,shape,axis", [(2, (24, 20), 0), (2, (24, 20), 1), (3, (12, 10, 14), 1),
+                                            (3, (12, 10, 14), 2)])
+def test_gradient_of_a_sine_wave(oracle_lib, dim, shape, axis):
+    """Right after dsm_set_liquid f = 0, so the velocity moment of Sec. II.B
+    is u = F / 2 with F = mu G[C2] (no body force, rho = 1): the oracle's u
+    over its own mu is G/2, which must be sin k cos kx along the wave and 0
+    across it."""
+    k, x, C2 = _axis_wave(dim, shape, axis, 3, 0.2, 0.45)
+    N = int(np.prod(shape))
+    o = O.Oracle(dim, shape, (0.0, 0.006, 0.004))
+    o.set_solid_field(np.zeros(N))
+    o.set_liquid(W.flat(C2))
+    mu = o.chemical_potential()
+    u = o.fields()["u"]
+    exact = math.sin(k) * 0.2 * np.cos(k * x)
+    for d in range(dim):
+        want = mu * W.flat(exact) / 2.0 if d == axis else np.zeros(N)
+        assert np.abs(u[d] - want).max() < 1e-16
+
+
+@pytest.mark.parametrize("dim,shape,dirn", [(2, (32, 32), (1, 1)), (2, (32, 32), (1, -1)),
+                                            (3, (16, 16, 16), (1, 1, 0)), (3, (16, 16, 16), (1, 1, 1))])
+def test_laplacian_is_isotropic(oracle_lib, dim, shape, dirn):
+    """Isotropy (Sec. II.B): for a long wave along a diagonal, L[sin(k.x)]
+    = -|k|^2 sin(k.x) to leading order, with a relative error of order
+    |k|^2 / 12 (here below 3 %); a stencil missing its diagonal links is off
+    by a factor of order one."""
+    N = int(np.prod(shape))
+    X = np.meshgrid(*[np.arange(n, dtype=float) for n in shape], indexing="ij")
+    kv = np.array(dirn, float) * 2.0 * math.pi / shape[0]
+    phase = sum(kv[d] * X[d] for d in range(dim))
+    C2 = 0.4 + 0.1 * np.sin(phase)
+    kap = (0.0, 0.006, 0.004)
+    mus = []
+    for alpha in (1.0, 2.0):
+        o = O.Oracle(dim, shape, kap, alpha=alpha)
+        o.set_solid_field(np.zeros(N))
+        o.set_liquid(W.flat(C2))
+        mus.append(o.chemical_potential())
+    lap = (mus[0] - mus[1]) / (3.0 * (kap[1] + kap[2]))
+    cont = W.flat(-(kv @ kv) * 0.1 * np.sin(phase))
+    rel = np.abs(lap - cont).max() / np.abs(cont).max()
+    assert rel < (kv @ kv) / 12.0 * 1.2
+    assert rel > 0.0
+
+
+# --- interpolated bounce-back with the wall off the half-way position -------
+#
+# Sec. II.B: links cut by the diffuse wall use the linear interpolated
+# bounce-back of Bouzidi et al. with the wall distance from the tanh profile
+# (eqn:tanh).  A channel whose C1 = 1/2 planes sit at y = 3.7 and y = 40.8
+# gives q = 0.3 at the bottom (the q < 1/2 branch) and q = 0.8 at the top
+# (the q >= 1/2 branch).  Full of liquid (C2 = 1 - C1, theta = 90 deg) and
+# driven by the body force F = C2 g along x, the steady flow solves
+#   nu u'' = -C2(y) g,   u(3.7) = u(40.8) = 0,   nu = (tau - 1/2) / 3,
+# whose solution is u = (g / nu) [A (y - ya) - int_ya^y (y - t) C2(t) dt].
+
+YA, YB, NY = 3.7, 40.8, 48
+
+
+def _channel(bounce):
+    nx, g, tau = 4, 1e-6, 1.0
+    shape = (nx, NY)
+    _, Y = np.meshgrid(np.arange(nx, dtype=float), np.arange(NY, dtype=float), indexing="ij")
+    C1 = W.tanh_profile(W.periodic_slab_distance(Y, YB, NY + YA, NY))
+    C2 = 1.0 - C1
+    k = W.kappas_for_angle(90.0)
+    if bounce == "oracle":
+        sim = O.Oracle(2, shape, k, tau=tau, gravity=(g, 0, 0))
+        sim.set_solid_field(W.flat(C1))
+        sim.set_liquid(W.flat(C2))
+    else:
+        sim = MiniOracle(2, shape, k, tau=tau, gravity=(g, 0, 0), bounce="halfway")
+        sim.set_solid_field(C1)
+        sim.set_liquid(C2)
+    sim.step(16000)
+    u = np.asarray(sim.fields()["u"][0]).reshape(shape, order="F")[0]
+    return sim, C1[0], u, g, tau
+
+
+def _channel_closed_form(g, tau, y):
+    nu = (tau - 0.5) / 3.0
+    t = np.linspace(YA, YB, 200001)
+    C2 = 0.5 + 0.5 * np.tanh(np.minimum(t - YA, YB - t) / 2.0)   # 1 - C1 in the channel
+    dt = t[1] - t[0]
+    I1 = np.concatenate([[0.0], np.cumsum(0.5 * (C2[1:] + C2[:-1]) * dt)])      # int_ya^s C2
+    I2 = np.concatenate([[0.0], np.cumsum(0.5 * (I1[1:] + I1[:-1]) * dt)])      # int_ya^y I1
+    Acoef = I2[-1] / (YB - YA)
+    return g / nu * (Acoef * (y - YA) - np.interp(y, t, I2))
+
+
+def test_off_grid_channel_has_both_bouzidi_branches(oracle_lib):
+    """q = 0.3 on every link leaving the first fluid row towards the bottom
+    wall and q = 0.8 towards the top wall, axis and diagonal links alike."""
+    shape = (4, NY)
+    _, Y = np.meshgrid(np.arange(4.0), np.arange(float(NY)), indexing="ij")
+    C1 = W.tanh_profile(W.periodic_slab_distance(Y, YB, NY + YA, NY))
+    o = O.Oracle(2, shape, W.kappas_for_angle(90.0))
+    o.set_solid_field(W.flat(C1))
+    c, _ = O.lattice(2)
+    for x in range(4):
+        for kdir in range(1, 9):
+            if c[kdir][1] == -1:
+                assert o.link_q(x + 4 * 4, kdir) == pytest.approx(0.3, abs=1e-9)
+            if c[kdir][1] == 1:
+                assert o.link_q(x + 4 * 40, kdir) == pytest.approx(0.8, abs=1e-9)
+
+
+def test_off_grid_channel_flow_matches_closed_form(oracle_lib):
+    """The oracle's steady profile over the fluid rows is within 0.3 % of
+    the closed form (relative to the peak speed; measured 0.07 %); halfway
+    bounce-back, which puts the walls at 3.5 and 40.5, misses it by 3 %, and
+    so would interpolation with q and 1 - q exchanged or either branch's
+    weights misplaced."""
+    _, C1, u, g, tau = _channel("oracle")
+    fluid = C1 < 0.5
+    y = np.arange(NY, dtype=float)[fluid]
+    ua = _channel_closed_form(g, tau, y)
+    err = np.abs(u[fluid] - ua).max() / ua.max()
+    assert err < 3e-3, err
+    _, _, uh, _, _ = _channel("halfway")
+    err_h = np.abs(uh[fluid] - ua).max() / ua.max()
+    assert err_h > 2e-2, err_h
+
+
+# --- two-step solid initialisation (Sec. II.B) -------------------------------
+
+def _sharp_mask(shape):
+    """An L-shaped solid with convex and concave corners on a base slab."""
+    m = np.zeros(shape, np.uint8)
+    m[:, :6] = 1
+    m[10:30, 6:26] = 1
+    m[10:18, 26:40] = 1
+    return m
+
+
+def test_remask_redefines_the_solid_region(oracle_lib):
+    """After a run with REMASK, S is {C1 > 1/2} exactly (strict, as the
+    paper redefines the solid locations), so the confining potential is
+    inactive at every node: the solid-stage energy with beta equals the one
+    with beta = 0.  Without REMASK the corners of the sharp mask leave nodes
+    where it is active.  The amount of solid is conserved through both runs
+    of the two-step procedure."""
+    shape = (40, 48)
+    mask = _sharp_mask(shape)
+    k = W.kappas_for_angle(90.0)
+    res = {}
+    for flags in (O.SOLID_RESET, O.SOLID_RESET | O.SOLID_REMASK):
+        o = O.Oracle(2, shape, k, mask=W.flat(mask), threads=2)
+        o.init_solid(300, 1e-2, 2e-3, flags=flags)
+        m1 = o.mass()[0]
+        C1 = o.fields()["C1"]
+        S = o.mask()
+        F_beta, _ = o.free_energy()
+        o.init_solid(0, 0.0, 2e-3, flags=0)
+        F_free, _ = o.free_energy()
+        res[flags] = (C1, S, F_beta, F_free, m1, o)
+    C1, S, Fb, Ff, m1, o = res[O.SOLID_RESET | O.SOLID_REMASK]
+    assert np.array_equal(S.astype(bool), C1 > 0.5)
+    assert Fb == Ff
+    C1n, Sn, Fbn, Ffn, _, _ = res[O.SOLID_RESET]
+    assert np.array_equal(Sn, W.flat(mask))
+    assert np.count_nonzero((C1n > 0.5) != Sn.astype(bool)) > 0
+    assert Fbn > Ffn
+    # second run of the two-step procedure, confined by the new S
+    o.init_solid(500, 1e-3, 2e-4, flags=0)
+    assert abs(o.mass()[0] - m1) / m1 < 1e-12
+
+
+def test_remask_keeps_corners_the_first_run_rounded(oracle_lib):
+    """The point of the two-step procedure: the second run is confined by the
+    rounded solid of the first, not by the sharp mask.  Continued without
+    REMASK, the confinement keeps pulling the corners back towards the sharp
+    mask, so that run ends closer to the mask than the two-step one."""
+    shape = (40, 48)
+    mask = _sharp_mask(shape)
+    k = W.kappas_for_angle(90.0)
+    ends = []
+    for first in (O.SOLID_RESET | O.SOLID_REMASK, O.SOLID_RESET):
+        o = O.Oracle(2, shape, k, mask=W.flat(mask), threads=2)
+        o.init_solid(300, 1e-2, 2e-3, flags=first)
+        S1 = o.fields()["C1"] > 0.5
+        o.init_solid(1500, 2e-2, 2e-4, flags=0)
+        ends.append((S1, o.fields()["C1"] > 0.5))
+    (S1r, endr), (S1n, endn) = ends
+    assert np.array_equal(S1r, S1n)  # the flag acts after the first run only
+    sharp = W.flat(mask).astype(bool)
+    assert np.count_nonzero(endn != sharp) + 10 < np.count_nonzero(endr != sharp)
+
+
+# --- the two forms of the surface-tension force -----------------------------
+
+def test_both_force_forms_reach_the_same_static_drop(oracle_lib):
+    """Sec. II.B states F_s = -C grad mu and writes the velocity moment with
+    mu grad C.  The two differ by grad(C mu), a pressure term, so a static
+    equilibrium is the same for both: a D2Q9 sessile drop at 90 degrees
+    (80 x 48, 6-node wall, R = 14) held for 15000 steps keeps the same angle
+    within 0.1 degree and the same concentrations within 2e-3 under either
+    form (measured: 0.03 degree, 1e-3).  The form used throughout is
+    mu grad C."""
+    shape = (80, 48)
+    w = W.sessile_drop(2, shape, 6, 14.0, 90.0)
+    out = []
+    for fr in (O.FORCE_POTENTIAL, O.FORCE_AS_TYPESET):
+        o = O.Oracle(2, shape, w.kappa, force_reading=fr, threads=4)
+        o.set_solid_field(W.flat(w.C1))
+        o.set_liquid(W.flat(w.C2))
+        o.step(15000)
+        fl = o.fields()
+        th = A.contact_angle(W.unflat(fl["C1"], shape), W.unflat(fl["C2"], shape), 1, w.wall_level)
+        out.append((th, fl["C2"], float(np.abs(fl["u"]).max())))
+    (t0, c0, u0), (t1, c1, u1) = out
+    assert abs(t0 - t1) < 0.1, (t0, t1)
+    assert abs(t0 - 90.0) < 1.0
+    assert np.abs(c0 - c1).max() < 2e-3
+    assert u0 < 3e-5 and u1 < 3e-5, (u0, u1)
