@@ -286,3 +286,50 @@ def test_both_force_forms_reach_the_same_static_drop(oracle_lib):
     assert abs(t0 - 90.0) < 1.0
     assert np.abs(c0 - c1).max() < 2e-3
     assert u0 < 3e-5 and u1 < 3e-5, (u0, u1)
+
+
+def _force_golden():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "force_reading_d2q9_128x64_theta60.json")
+    return json.load(open(path))
+
+
+def test_typeset_force_form_grows_a_velocity_mode():
+    """Why mu grad C: on the 128 x 64 contact-angle drop at the paper's
+    tau = 1 and gamma = 2.5e-3 (stored FP64 oracle history, written by
+    tests/golden/make_force_reading_golden.py), the largest speed under
+    mu grad C falls monotonically while the drop spreads towards 60 degrees;
+    under the typeset -C grad mu it follows the same course for about
+    6 x 10^4 steps, then a velocity mode grows by three orders of magnitude
+    and tears the drop apart (the fitted angle passes 150 degrees)."""
+    h = _force_golden()["history"]
+    pot = [e["umax"] for e in h["potential"]]
+    typ = [e["umax"] for e in h["typeset"]]
+    assert all(b <= a for a, b in zip(pot[3:], pot[4:]))
+    assert h["potential"][-1]["theta"] < 63.0
+    k_min = int(np.argmin(typ))
+    assert 40000 <= h["typeset"][k_min]["step"] <= 80000
+    assert typ[-1] > 1000.0 * typ[k_min]
+    assert h["typeset"][-1]["theta"] > 150.0
+    # the two agree while the mode is small
+    for a, b in zip(h["potential"][:8], h["typeset"][:8]):
+        assert abs(a["theta"] - b["theta"]) < 0.5
+
+
+def test_force_golden_matches_current_oracle(oracle_lib):
+    """The stored histories are the current oracle's: the first record of
+    each form is reproduced."""
+    g = _force_golden()
+    w = W.config_2d_contact_angle(60.0)
+    for name, fr in (("potential", O.FORCE_POTENTIAL), ("typeset", O.FORCE_AS_TYPESET)):
+        o = O.Oracle(2, w.shape, w.kappa, mobility=w.mobility, tau=w.tau, threads=4, force_reading=fr)
+        o.set_solid_field(W.flat(w.C1))
+        o.set_liquid(W.flat(w.C2))
+        o.step(g["every"])
+        fl = o.fields()
+        th = A.contact_angle(W.unflat(fl["C1"], w.shape), W.unflat(fl["C2"], w.shape), 1, w.wall_level)
+        assert th == pytest.approx(g["history"][name][0]["theta"], abs=1e-9)
+        assert float(np.sqrt((fl["u"] ** 2).sum(axis=0)).max()) == pytest.approx(
+            g["history"][name][0]["umax"], rel=1e-9)
