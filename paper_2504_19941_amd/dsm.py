@@ -25,8 +25,7 @@ DSM_STORAGE_FP32, DSM_STORAGE_FP16 = 0, 1
 EXPORTED = [
     "dsm_required_bytes", "dsm_create", "dsm_init_solid", "dsm_set_solid_field", "dsm_set_liquid",
     "dsm_set_gravity", "dsm_step", "dsm_step_timed", "dsm_free_energy", "dsm_mass", "dsm_diagnostics",
-    "dsm_solid_region", "dsm_fields",
-    "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
+    "dsm_solid_region", "dsm_fields", "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
     "dsm_state_bytes", "dsm_get_state", "dsm_set_state", "dsm_step_count", "dsm_set_tiling",
     "dsm_get_tiling", "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
     "dsm_batch_required_bytes", "dsm_batch_create", "dsm_batch_set_schedule", "dsm_batch_get_schedule",
@@ -222,11 +221,15 @@ def dsm_mass(h):
     return m
 
 
+def _diag_dict(d):
+    return {"mass": np.array(d.mass[:]), "free_energy": d.free_energy, "kinetic_energy": d.kinetic_energy,
+            "max_speed": d.max_speed, "nonfinite_nodes": d.nonfinite_nodes}
+
+
 def dsm_diagnostics(h):
     d = dsm_diag()
     _check(load().dsm_diagnostics(h, ctypes.byref(d)), "dsm_diagnostics")
-    return {"mass": np.array(d.mass[:]), "free_energy": d.free_energy, "kinetic_energy": d.kinetic_energy,
-            "max_speed": d.max_speed, "nonfinite_nodes": d.nonfinite_nodes}
+    return _diag_dict(d)
 
 
 def dsm_solid_region(h, N):

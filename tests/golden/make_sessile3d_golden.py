@@ -56,7 +56,9 @@ def run(theta, steps, threads, out=None):
     hist = []
     t0 = time.time()
     for k in range(steps // EVERY):
-        o.step(EVERY)
+        for part in range(EVERY // 500):
+            o.step(500)
+            print(f"theta {theta:g}: step {k * EVERY + (part + 1) * 500} ({time.time() - t0:.0f} s)", flush=True)
         fl = o.fields()
         th = A.contact_angle(W.unflat(fl["C1"], w.shape), W.unflat(fl["C2"], w.shape), 2, w.wall_level)
         F, E = o.free_energy()
