@@ -209,6 +209,20 @@ typedef struct {
 } dsm_diag;
 int dsm_diagnostics(dsm_sim* s, dsm_diag* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * results as dsm_diagnostics, bit for bit (the same kernels and grid), with
+ * the reduction's workspace -- 1024 rows of 8 FP64 partial sums plus the 8
+ * final sums, 65 600 bytes -- taken from a static device array that the
+ * library holds on each GPU it runs on until the process ends, instead of
+ * from the handle's buffer.  The workspace does not grow with the lattice,
+ * so every lattice a handle accepts fits.  No call allocates or frees device
+ * or pinned memory.  Calls on one GPU share the array: calls that overlap on
+ * one GPU (from several threads or streams) race.  Synchronises the handle's
+ * stream.  Errors: DSM_EINVAL (NULL argument), DSM_ESTATE (no live state),
+ * DSM_EDEVICE. */
+int dsm_diagnostics_noalloc(dsm_sim* s, dsm_diag* out);
+
 /* The solid region S the confining potential currently holds the solid to
  * (Sec. II.A; host, N bytes in node order, 1 in S): the mask given to
  * dsm_create, or {C1 > 1/2} after a solid stage run with DSM_SOLID_REMASK

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -873,3 +874,90 @@ int dsm_destroy(dsm_sim* s) {
 const char* dsm_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+// ---- Diagnostics without device allocation --------------------------------
+//
+// dsm_diagnostics_noalloc runs the same two reduction kernels as
+// dsm_diagnostics, with the same grid, so its sums are bit-identical, but
+// takes their workspace (one row of RED_SLOTS FP64 partial sums per reduction
+// block, then the RED_SLOTS final values) from `scratch` below instead of the
+// handle's buffer.  `scratch` is a file-scope device array: each GPU the
+// library runs on holds its own copy, with the code object, until the process
+// ends.  Host code never uses the array's name as an address; it uses the
+// device address hipGetSymbolAddress returns, looked up once per device with
+// that device current.  Every block writes its whole row and the final kernel
+// reads only the rows of this call, so nothing has to start at zero; two calls
+// that overlap on one GPU share the array and race.
+
+namespace {
+
+// The reduction grid never exceeds kReduceBlocks blocks, whatever the
+// lattice, so this fixed workspace (65 600 bytes) fits every handle.
+constexpr int kNoAllocPartials = kReduceBlocks;
+constexpr size_t kNoAllocDoubles = (size_t)(kNoAllocPartials + 1) * RED_SLOTS;
+constexpr int kMaxDevices = 64;
+static_assert(kNoAllocPartials >= kReduceBlocks, "workspace must hold a partial row per reduction block");
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that runs `stream`.
+int scratch_address(hipStream_t stream, double** out) {
+    int dev = 0;
+    if (stream) {
+        hipDevice_t d = 0;
+        HIP_TRY(hipStreamGetDevice(stream, &d));
+        dev = (int)d;
+    } else {
+        HIP_TRY(hipGetDevice(&dev));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(DSM_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess)
+            return fail(DSM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DSM_OK;
+}
+
+}  // namespace
+
+int dsm_diagnostics_noalloc(dsm_sim* s, dsm_diag* out) {
+    if (!s || !out) return fail(DSM_EINVAL, "NULL argument");
+    if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
+    double* ws = nullptr;
+    int rc = scratch_address(s->stream, &ws);
+    if (rc) return rc;
+    rc = observe(s);
+    if (rc) return rc;
+    double* partials = ws;
+    double* red = ws + (size_t)kNoAllocPartials * RED_SLOTS;
+    const Phys ph = make_phys(s, s->stage);
+    HIP_TRY(launch_reduce(s->p.dim, s->geom, ph, s->d.c1, s->d.phi, s->d.mask, s->d.aux, PG(s, s->cur), s->pull,
+                          partials, red, s->stream));
+    double r[RED_SLOTS];
+    HIP_TRY(hipMemcpyAsync(r, red, sizeof(r), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    out->mass[0] = r[RED_C1];
+    out->mass[1] = r[RED_C2];
+    out->mass[2] = r[RED_C3];
+    out->free_energy = r[RED_FREE];
+    out->kinetic_energy = r[RED_EKIN];
+    out->max_speed = r[RED_UMAX];
+    out->nonfinite_nodes = r[RED_NONFINITE];
+    return DSM_OK;
+}

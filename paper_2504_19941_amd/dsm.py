@@ -25,7 +25,7 @@ DSM_STORAGE_FP32, DSM_STORAGE_FP16 = 0, 1
 EXPORTED = [
     "dsm_required_bytes", "dsm_create", "dsm_init_solid", "dsm_set_solid_field", "dsm_set_liquid",
     "dsm_set_gravity", "dsm_step", "dsm_step_timed", "dsm_free_energy", "dsm_mass", "dsm_diagnostics",
-    "dsm_solid_region", "dsm_fields", "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
+    "dsm_diagnostics_noalloc", "dsm_solid_region", "dsm_fields", "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
     "dsm_state_bytes", "dsm_get_state", "dsm_set_state", "dsm_step_count", "dsm_set_tiling",
     "dsm_get_tiling", "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
     "dsm_batch_required_bytes", "dsm_batch_create", "dsm_batch_set_schedule", "dsm_batch_get_schedule",
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.dsm_free_energy.argtypes = [vp, _dp, _dp]
     lib.dsm_mass.argtypes = [vp, _dp]
     lib.dsm_diagnostics.argtypes = [vp, ctypes.POINTER(dsm_diag)]
+    lib.dsm_diagnostics_noalloc.argtypes = [vp, ctypes.POINTER(dsm_diag)]
     lib.dsm_solid_region.argtypes = [vp, vp]
     lib.dsm_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
     lib.dsm_chemical_potential.argtypes = [vp, _dp]
@@ -229,6 +230,12 @@ def _diag_dict(d):
 def dsm_diagnostics(h):
     d = dsm_diag()
     _check(load().dsm_diagnostics(h, ctypes.byref(d)), "dsm_diagnostics")
+    return _diag_dict(d)
+
+
+def dsm_diagnostics_noalloc(h):
+    d = dsm_diag()
+    _check(load().dsm_diagnostics_noalloc(h, ctypes.byref(d)), "dsm_diagnostics_noalloc")
     return _diag_dict(d)
 
 
