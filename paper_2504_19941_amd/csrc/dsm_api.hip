@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
@@ -298,6 +299,21 @@ int build_links(dsm_sim* s) {
     if (count[1] > cap)
         return fail(DSM_EINVAL, "solid surface has more cut links than the table holds (" +
                                     std::to_string(count[1]) + " > " + std::to_string(cap) + ")");
+    // Order the records by the slot they write.  A slot index runs along x
+    // within one direction row of one lattice row, so consecutive threads of
+    // the link kernel then read and write neighbouring elements (the records
+    // come out of the search in the order its atomics happened to run, which
+    // scatters every wave's accesses over the lattice).  Each slot has one
+    // record, so the order changes no result.
+    if (count[1] > 1) {
+        std::vector<LinkRec> h((size_t)count[1]);
+        const size_t bytes = h.size() * sizeof(LinkRec);
+        HIP_TRY(hipMemcpyAsync(h.data(), s->d.links, bytes, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        std::sort(h.begin(), h.end(), [](const LinkRec& a, const LinkRec& b) { return a.dst < b.dst; });
+        HIP_TRY(hipMemcpyAsync(s->d.links, h.data(), bytes, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
     s->nlinks = count[1];
     return DSM_OK;
 }
