@@ -70,11 +70,12 @@ def bytes_per_launch(Q: int, pop_bytes: int, fluid_nodes: int, solid_nodes: int)
     return fluid_nodes * bytes_per_node(Q, pop_bytes, False) + solid_nodes * bytes_per_node(Q, pop_bytes, True)
 
 
-def measured_traffic(summary: str, workload: str, tag: str = ""):
+def measured_traffic(summary: str, workload: str, tag: str = "", tiling=None):
     """HBM bytes per launch of the fused kernel from a committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the factor measured on
     a plain copy kernel; tag "" for FP32 storage, "_fp16" for FP16), or None
-    if absent, taken on another workload or on other kernel source."""
+    if absent, taken on another workload, on other kernel source or, when the
+    summary records it, with another launch shape than ``tiling``."""
     path = PMC_SUMMARY[summary]
     if not os.path.exists(path):
         return None
@@ -85,6 +86,9 @@ def measured_traffic(summary: str, workload: str, tag: str = ""):
         return m.group(1) if m else None
 
     if field("workload") != workload or field("kernel_source_sha256") != kernel_source_hash():
+        return None
+    recorded = re.search(rf"^tiling{tag}:\s*(\d+)\s+(\d+)", text, re.M)
+    if tiling is not None and recorded and (int(recorded.group(1)), int(recorded.group(2))) != tuple(tiling):
         return None
     try:
         return float(field("hbm_bytes_per_launch" + tag))
@@ -542,9 +546,9 @@ def main():
         sessile = storage_block(s32, ws.nodes)
         sessile.update({"workload": ws.name, "shape": list(ws.shape),
                         "fluid_node_fraction": round((ws.nodes - s_solid) / ws.nodes, 4),
-                        "traffic": measured_traffic("sessile", ws.name)})
+                        "traffic": measured_traffic("sessile", ws.name, "", s32["tiling"])})
         sessile["fp16_store"] = storage_block(s16, ws.nodes)
-        sessile["fp16_store"]["traffic"] = measured_traffic("sessile", ws.name, "_fp16")
+        sessile["fp16_store"]["traffic"] = measured_traffic("sessile", ws.name, "_fp16", s16["tiling"])
         sessile["fp16_store"]["speedup_vs_fp32"] = round(s16["mlups"] / s32["mlups"], 3)
 
     stream_ref = None if args.no_stream_reference else stream_reference(dev)
@@ -601,7 +605,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": measured_traffic("pillars", w.name),
+            "traffic": measured_traffic("pillars", w.name, "", r32["tiling"]),
             "algorithmic_bytes": r32["alg_bytes"],
             "kernel": "k_step_fused<3,...> (one launch per step), 256x256x192 pillars, FP32",
             "stream_reference": stream_ref,
@@ -609,7 +613,7 @@ def main():
         },
     }
     out["fp16_store"] = storage_block(r16, N)
-    out["fp16_store"]["traffic"] = measured_traffic("pillars", w.name, "_fp16")
+    out["fp16_store"]["traffic"] = measured_traffic("pillars", w.name, "_fp16", r16["tiling"])
     out["fp16_store"]["speedup_vs_fp32"] = round(r16["mlups"] / r32["mlups"], 3)
     if sessile is not None:
         out["d3q19_128cube"] = sessile

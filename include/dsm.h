@@ -259,9 +259,9 @@ long long dsm_step_count(const dsm_sim* s);
  * 2D: 0 = 256, 1 = 128, 2 = 64 columns) and the number of planes (1..4096)
  * each workgroup marches through along the slowest axis.  Every choice
  * computes bit-identical populations (each node's arithmetic does not depend
- * on the tile).  Defaults: 3D variant 2 with the march of 8, 16 or 32
- * planes that takes the fewest whole rounds of tiles (at the kernel's tiles
- * per compute unit) times planes; 2D variant 0 with 16 planes, or 8 when the
+ * on the tile).  Defaults: 3D variant 2 with the march of 8, 16, 32, 48, 64,
+ * 96 or 128 planes that takes the fewest whole rounds of tiles (at the
+ * kernel's tiles per compute unit) times planes; 2D variant 0 with 16 planes, or 8 when the
  * lattice has too few 256-column tiles to give every compute unit whole
  * rounds of 16-plane marches.  dsm_create replaces that default by another
  * variant and a march of 8, 16 or 32 planes when a model of the step's

@@ -361,12 +361,15 @@ int check_flag(dsm_sim* s) {
 // Default march of the default tile (3D variant 2, 2D variant 0), for a chip
 // of `slots` tile slots (CUs x tiles resident per CU).
 //
-// 3D: of 8, 16 and 32 planes, the march that takes the fewest whole rounds of
-// tiles times planes, each march's two fill planes counted as 0.36 of a plane
-// (ties go to the longer march, which re-reads fewer fill planes).  Measured
-// on MI355X: 128 x 256 x 128 FP32 at 17.5 GLUPS with 32 planes against 16.9
-// with 16; 256 x 256 x 192 FP16 at 24.2 with 16 against 22.9 with 8; 80^3
-// FP32 at 9.8 with 8 against 6.5 with 16; 128^3 keeps 16 (FP32) and 8 (FP16).
+// 3D: of marches of 8 to 128 planes, the one that takes the fewest whole
+// rounds of tiles times planes, each march's two fill planes counted as 0.36
+// of a plane (ties go to the longer march, which re-reads fewer fill planes).
+// Measured on MI355X: 128 x 256 x 128 FP32 at 17.5 GLUPS with 32 planes
+// against 16.9 with 16; 80^3 FP32 at 9.8 with 8 against 6.5 with 16; the
+// 256 x 256 x 192 pillar lattice with 96 planes in FP32 (one round of 256
+// tiles: 736.9 us against 771.1 with 32) and 48 in FP16 (one round at two
+// tiles per CU: 481.2 us against 489.4 with 16); 128^3 keeps 16 (FP32) and 8
+// (FP16).
 //
 // 2D: 16 rows when the grid fills every slot in whole rounds, the last at
 // least 80 % busy, else 8: rows of 1000 columns keep 16, narrower ones gain
@@ -384,10 +387,10 @@ int default_planes(const Geom& g, int dim, int slots) {
     }
     double best = 0.0;
     int planes = 16;
-    for (int p : {32, 16, 8}) {
+    for (int p : {128, 96, 64, 48, 32, 16, 8}) {
         const long long n = tiles * ((g.Z + p - 1) / p);
         const double t = (double)((n + slots - 1) / slots) * ((p < g.Z ? p : g.Z) + 0.72);
-        if (p == 32 || t < best - 1e-9) best = t, planes = p;
+        if (p == 128 || t < best - 1e-9) best = t, planes = p;
     }
     return planes;
 }

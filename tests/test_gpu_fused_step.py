@@ -92,18 +92,22 @@ def test_default_tiling_and_its_readback(gpu):
     chose, then whatever dsm_set_tiling set.  On a 256-CU MI355X the defaults
     of the benchmark-type lattices are the measured best ones: 128x4 tiles
     marching 16 planes for the 128^3 FP32 lattice and 8 with FP16 storage;
-    8 planes for an 80^3 FP32 lattice, too small to fill the chip with 16;
+    96 planes (FP32) and 48 (FP16) for the 256 x 256 x 192 pillar lattice,
+    one round of tiles each; 8 planes for an 80^3 FP32 lattice, too small
+    to fill the chip with 16;
     64-column tiles with 8-row marches for a D2Q9 lattice 300 columns wide."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     cases = [(3, (128, 128, 128), dsm.DSM_STORAGE_FP32, (2, 16)),
              (3, (128, 128, 128), dsm.DSM_STORAGE_FP16, (2, 8)),
+             (3, (256, 256, 192), dsm.DSM_STORAGE_FP32, (2, 96)),
+             (3, (256, 256, 192), dsm.DSM_STORAGE_FP16, (2, 48)),
              (3, (80, 80, 80), dsm.DSM_STORAGE_FP32, (2, 8)),
              (2, (300, 8192), dsm.DSM_STORAGE_FP32, (2, 8))]
     for dim, shape, storage, expect in cases:
         sim = dsm.Simulation(dim, shape, KAPPA, storage=storage)
         variant, planes = sim.tiling()
-        assert 0 <= variant < dsm.dsm_tiling_variants(dim) and planes in (8, 16, 32)
+        assert 0 <= variant < dsm.dsm_tiling_variants(dim) and planes in (8, 16, 32, 48, 64, 96, 128)
         if cus == 256:
             assert (variant, planes) == expect, (shape, storage, (variant, planes))
         sim.set_tiling(0, 12)
