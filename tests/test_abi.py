@@ -165,3 +165,27 @@ def test_batch_calls_reject_invalid_arguments_without_a_device(lib):
     assert lib.dsm_batch_size(None) == -1
     assert lib.dsm_batch_items(None, 2) == -1
     assert lib.dsm_batch_destroy(None) == dsm.DSM_EINVAL
+
+
+def test_size_limits_are_checked_on_host(lib):
+    """The largest lattices: a plane of populations must stay below 2 GiB
+    (32-bit buffer offsets within a plane) and the lattice below 2^32
+    population slots; beyond either limit the size is 0 and dsm_create
+    fails with DSM_EINVAL before touching the device."""
+    # 3D plane: (nx + 64) * ny * 19 * 4 bytes
+    ok = dsm.make_params(3, (4096, 6000, 4), (0.01, 0.005, 0.01))
+    assert dsm.dsm_required_bytes(ok) > 0
+    big_plane = dsm.make_params(3, (8192, 3500, 4), (0.01, 0.005, 0.01))
+    assert dsm.dsm_required_bytes(big_plane) == 0
+    h = ctypes.c_void_p()
+    rc = lib.dsm_create(ctypes.byref(big_plane), None, ctypes.c_void_p(256), ctypes.c_size_t(1 << 50), None,
+                        ctypes.byref(h))
+    assert rc == dsm.DSM_EINVAL and "2 GiB" in dsm.dsm_last_error()
+    # total slots: (nx + 64) * ny * nz * 19 > 2^32 - 1
+    many = dsm.make_params(3, (1024, 1024, 256), (0.01, 0.005, 0.01))
+    assert dsm.dsm_required_bytes(many) == 0
+    rc = lib.dsm_create(ctypes.byref(many), None, ctypes.c_void_p(256), ctypes.c_size_t(1 << 50), None,
+                        ctypes.byref(h))
+    assert rc == dsm.DSM_EINVAL and "2^32" in dsm.dsm_last_error()
+    # a 2D lattice of 2^28 nodes is fine (planes are single rows)
+    assert dsm.dsm_required_bytes(dsm.make_params(2, (16384, 16384), (0.01, 0.005, 0.01))) > 0
