@@ -243,11 +243,23 @@ def run_batch(dsm, W, dev, args):
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1) / args.batch_steps
     print(f"bench.py: batched form: one lattice at a time {plain_ms:.3f} ms/step", file=sys.stderr, flush=True)
-    # (b) batched
+    # (b) batched: the modelled tuner's schedule, then the measured tuner's
     batch = dsm.Batch(sims, device=dev)
     tune_t0 = time.perf_counter()
     cost2, _ = batch.tune()
     tune_s = time.perf_counter() - tune_t0
+    batch.step(args.warmup)
+    model_sched = batch.schedule(2)
+    model_ms = batch.step_timed(args.batch_steps)
+    print(f"bench.py: batched form: modelled schedule {model_sched} {model_ms:.4f} ms/step", file=sys.stderr,
+          flush=True)
+    steps0 = sims[0].steps
+    mtune_t0 = time.perf_counter()
+    measured_ms, _ = batch.tune(reps=5)
+    mtune_s = time.perf_counter() - mtune_t0
+    tune_steps = sims[0].steps - steps0
+    print(f"bench.py: batched form: measured tuner {batch.schedule(2)} {measured_ms:.4f} ms/step "
+          f"({tune_steps} steps, {mtune_s:.2f} s)", file=sys.stderr, flush=True)
     batch.step(args.warmup)
     wall0 = time.perf_counter()
     ms = batch.step_timed(args.batch_steps)
@@ -266,9 +278,12 @@ def run_batch(dsm, W, dev, args):
         "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes": alg,
         "schedule": batch.schedule(2),
+        "tuner": "measured (every candidate timed on the batch itself, 5 steps each)",
+        "tune_s": round(mtune_s, 3),
+        "tune_steps": tune_steps,
         "items": batch.items(2),
-        "modelled_cost": round(cost2, 1),
-        "tune_s": round(tune_s, 3),
+        "modelled_choice": {"schedule": model_sched, "modelled_cost": round(cost2, 1), "tune_s": round(tune_s, 4),
+                            "value": round(nodes / (model_ms * 1e-3) / 1e6, 2), "ms_per_step": round(model_ms, 5)},
         "one_lattice_at_a_time": {"value": round(nodes / (plain_ms * 1e-3) / 1e6, 2), "unit": "MLUPS",
                                   "ms_per_step": round(plain_ms, 5)},
         "speedup_vs_one_at_a_time": round(plain_ms / ms, 3),

@@ -325,16 +325,24 @@ int dsm_batch_create(dsm_sim* const* sims, int count, void* dev_buf, size_t dev_
 int dsm_batch_set_schedule(dsm_batch* b, int dim, const dsm_batch_schedule* sched);
 int dsm_batch_get_schedule(const dsm_batch* b, int dim, dsm_batch_schedule* sched);
 
-/* Autotuner: for each lattice type present, scores every tile variant with
- * each of the plane counts 8, 16, 32, 64 and 128 by a model of the batched
- * step over the members' actual shapes (waves per work item, the resident
- * waves the dynamic queue keeps busy, the tail left by the longest item, and
- * a per-variant cost of one wave-plane fitted to step times measured on
- * MI355X), and installs the best.
- * No device work is issued, so the members' states and step counts are
- * unchanged.  reps must be 0 (timed tuning is not offered).  cost (may be
- * NULL) receives the modelled cost of the chosen schedule of each type
- * (index 0: 2D, 1: 3D; 0 where absent), in wave-plane units. */
+/* Autotuner, for each lattice type present (cost may be NULL; index 0: 2D,
+ * 1: 3D; 0 where absent).  reps in [0, 1000].
+ * reps == 0, modelled: scores every tile variant with each of the plane
+ * counts 4, 8, 16, 32, 64 and 128 by a model of the batched step over the
+ * members' actual shapes (waves per work item, the resident waves the
+ * dynamic queue keeps busy, the tail left by the longest item, and a
+ * per-variant cost of one wave-plane fitted to step times measured on
+ * MI355X), and installs the best.  No device work is issued, so the
+ * members' states and step counts are unchanged.  cost receives the
+ * modelled cost, in wave-plane units.
+ * reps > 0, measured: times every tile variant with each of those plane
+ * counts and each count of resident workgroups per CU (0 = as many as fit,
+ * then 1 .. min(fit - 1, 4)) on the batch itself: one untimed step, then
+ * reps steps between two HIP events, synchronising before the next
+ * candidate; installs the fastest.  Every member advances by 1 + reps steps
+ * per candidate (dsm_step_count tells how many); results stay those of the
+ * same lattices stepped alone.  cost receives the best time per step, in
+ * ms.  Errors: DSM_EINVAL, DSM_ESTATE, DSM_EUNSTABLE, DSM_EDEVICE. */
 int dsm_batch_tune(dsm_batch* b, int reps, double cost[2]);
 
 /* Advances every member by n steps (n >= 0), then synchronises and checks

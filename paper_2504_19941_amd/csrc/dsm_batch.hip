@@ -370,6 +370,43 @@ double dsm::lattice_schedule_cost(const Geom& g, int dim, int variant, int plane
     return kWaveCost[dim - 2][variant] * (total / resident_waves + kTailShare[dim - 2] * longest);
 }
 
+// Measured tuning: every candidate schedule of each lattice type present
+// (tile variant x march planes x resident workgroups per CU) is installed
+// and timed on the batch itself through the public calls: one untimed step,
+// then reps steps as graph replays between two events, the stream
+// synchronised before the next candidate.  The fastest is kept.  Workgroups
+// per CU: 0 (as many as fit) and each smaller count up to 4.
+static int tune_measured(dsm_batch* b, int reps, double cost[2]) {
+    for (int d = 0; d < 2; ++d) {
+        if (!b->present[2 * d] && !b->present[2 * d + 1]) continue;
+        const int dim = d == 0 ? 2 : 3;
+        dsm_batch_schedule best = b->sched[d];
+        double best_ms = 1e300;
+        for (int v = 0; v < fused_tile_variants(dim); ++v) {
+            int fit = 1;  // workgroups per CU the kernels of this type allow
+            for (int t = 2 * d; t < 2 * d + 2; ++t)
+                if (b->present[t]) fit = std::max(fit, batch_blocks_per_cu(dim, v, b->half, t & 1));
+            for (int planes : kTunePlanes)
+                for (int per_cu = 0; per_cu <= std::min(fit - 1, 4); ++per_cu) {
+                    const dsm_batch_schedule cand{v, planes, per_cu};
+                    int rc = dsm_batch_set_schedule(b, dim, &cand);
+                    if (!rc) rc = dsm_batch_step(b, 1);
+                    double ms = 0.0;
+                    if (!rc) rc = dsm_batch_step_timed(b, reps, &ms);
+                    if (rc) return rc;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = cand;
+                    }
+                }
+        }
+        const int rc = dsm_batch_set_schedule(b, dim, &best);
+        if (rc) return rc;
+        if (cost) cost[d] = best_ms;
+    }
+    return DSM_OK;
+}
+
 extern "C" {
 
 size_t dsm_batch_required_bytes(dsm_sim* const* sims, int count) {
@@ -452,10 +489,10 @@ int dsm_batch_get_schedule(const dsm_batch* b, int dim, dsm_batch_schedule* sche
 int dsm_batch_tune(dsm_batch* b, int reps, double cost[2]) {
     if (!b) return set_error(DSM_EINVAL, "batch is NULL");
     if (reps < 0 || reps > 1000) return set_error(DSM_EINVAL, "reps must be in [0, 1000]");
-    if (reps > 0) return set_error(DSM_EINVAL, "timed tuning is not available (reps must be 0)");
     if (cost) cost[0] = cost[1] = 0.0;
     int rc = refresh(b);
     if (rc) return rc;
+    if (reps > 0) return tune_measured(b, reps, cost);
     for (int d = 0; d < 2; ++d) {
         if (!b->present[2 * d] && !b->present[2 * d + 1]) continue;
         const int dim = d == 0 ? 2 : 3;

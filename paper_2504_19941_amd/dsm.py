@@ -348,8 +348,10 @@ def dsm_batch_get_schedule(b, dim):
 
 
 def dsm_batch_tune(b, reps=0):
-    """Installs the modelled best schedules; returns their modelled costs
-    (2D, 3D) in wave-plane units."""
+    """reps == 0: installs the modelled best schedules and returns their
+    modelled costs (2D, 3D) in wave-plane units.  reps > 0: times every
+    candidate schedule on the batch itself (the members advance by the steps
+    it takes), installs the fastest and returns its ms per step."""
     t = np.zeros(2)
     _check(load().dsm_batch_tune(b, int(reps), _p(t)), "dsm_batch_tune")
     return float(t[0]), float(t[1])

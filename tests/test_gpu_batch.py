@@ -1,6 +1,7 @@
 """Batched form on the GPU: each member of a batch of uneven 2D and 3D
 lattices advances exactly (bit for bit) as it does alone under dsm_step,
-whatever the schedule; the tuner leaves the state untouched; a member
+whatever the schedule; the modelled tuner leaves the state untouched, the
+measured one advances it as single steps would; a member
 checked against the FP64 oracle directly; the error paths of the batch
 calls."""
 import ctypes
@@ -126,6 +127,30 @@ def test_tuner_keeps_state_and_results(gpu):
     batch.close()
 
 
+def test_measured_tuner_times_candidates_and_keeps_results(gpu):
+    """The measured tuner times every candidate schedule on the batch itself
+    and installs the fastest; the steps it takes leave the members where the
+    same number of single-lattice steps would."""
+    A = make_members(SPECS)
+    B = make_members(SPECS)
+    batch = dsm.Batch(A)
+    s0 = [s.steps for s in A]
+    ms2, ms3 = batch.tune(reps=2)
+    taken = [s.steps - k for s, k in zip(A, s0)]
+    print(f"  measured: 2D {batch.schedule(2)} {ms2:.4f} ms, 3D {batch.schedule(3)} {ms3:.4f} ms; "
+          f"{taken[0]} steps taken", flush=True)
+    assert ms2 > 0.0 and ms3 > 0.0
+    assert len(set(taken)) == 1 and taken[0] >= 3 * 6 * 3
+    for s in B:
+        s.step(taken[0])
+    assert_same(A, B, "after measured tuning")
+    batch.step(3)
+    for s in B:
+        s.step(3)
+    assert_same(A, B, "stepping after measured tuning")
+    batch.close()
+
+
 def test_fp16_batch_matches_single_lattice_runs(gpu):
     A = make_members(SPECS, storage=dsm.DSM_STORAGE_FP16)
     B = make_members(SPECS, storage=dsm.DSM_STORAGE_FP16)
@@ -207,6 +232,8 @@ def test_batch_argument_errors(gpu):
     with pytest.raises(dsm.DsmError):
         batch.step(-1)
     with pytest.raises(dsm.DsmError):
-        batch.tune(reps=3)  # timed tuning is not offered
+        batch.tune(reps=1001)
+    with pytest.raises(dsm.DsmError):
+        batch.tune(reps=-1)
     batch.step(0)
     batch.close()
