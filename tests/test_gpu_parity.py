@@ -112,6 +112,42 @@ def test_solid_stage(gpu, dim, storage, bar):
     assert report("C1", fg["C1"], fo["C1"]) < bar
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_one_node_slit_bounce_back_fallback(gpu, dim, kernel):
+    """A fluid slit one node wide between two diffuse slabs (off-centre):
+    every cut link of the slit takes the q < 1/2 fallback to halfway
+    bounce-back or has q = 1/2 already, so sum f over the fluid nodes is
+    conserved; the GPU follows the oracle node by node over 40 steps."""
+    from oracle.oracle import lattice
+
+    shape = (150, 9) if dim == 2 else (37, 21, 9)
+    coords = np.meshgrid(*[np.arange(n, dtype=float) for n in shape], indexing="ij")
+    dz = np.abs(coords[-1] - 4.2)
+    C1 = f32(W.flat(W.tanh_profile(np.minimum(dz, shape[-1] - dz) - 0.5)))
+    fluid = C1 < 0.5
+    Q, N = (9, 19)[dim - 2], C1.size
+    _, w = lattice(dim)
+    rng = np.random.default_rng(43)
+    fs = f32(np.asarray(w)[:, None] * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, size=(Q, N))) * fluid)
+    gs = np.zeros((Q, N))
+    gs[0] = 0.3 * fluid
+    sim, orc = pair(dim, shape, kernel, kappa=W.kappas_for_angle(90.0), tau=0.8)
+    for s in (sim, orc):
+        s.set_solid_field(C1)
+        s.set_postcollision(fs, gs)
+        s.step(40)
+    s0 = fs[:, fluid].sum()
+    pg, po = sim.get_populations(), orc.get_populations()
+    drift = abs(pg[0][:, fluid].sum() - s0) / s0
+    print(f"  sum f over the slit: relative drift {drift:.2e} (oracle "
+          f"{abs(po[0][:, fluid].sum() - s0) / s0:.2e})", flush=True)
+    assert drift < 1e-5
+    assert report("f", pg[0][:, fluid], po[0][:, fluid]) < 2e-6
+    fg, fo = sim.fields(), orc.fields()
+    assert report("u", fg["u"][:, fluid], fo["u"][:, fluid]) < 2e-6
+
+
 def test_fused_matches_split(gpu):
     shape = (64, 40, 36)
     mask, C1, C2 = wall_and_particle(3, shape, seed=41)

@@ -195,6 +195,58 @@ def test_off_grid_channel_flow_matches_closed_form(oracle_lib):
     assert err_h > 2e-2, err_h
 
 
+# --- the bounce-back fallback: q < 1/2 with x + c_i solid (Sec. II.B) -------
+#
+# The first interpolating form needs f*_k(x + c_i), which exists only where
+# x + c_i is fluid; where it is solid the reading is the second form with q
+# raised to 1/2, i.e. halfway bounce-back, f_i(x) = f*_k(x).  In a one-node
+# fluid slit between two solid slabs (off-centre, so that G[C1] does not
+# vanish), every cut link of a slit node has x + c_i solid and is either in
+# that fallback (q < 1/2 towards the nearer wall) or at q = 1/2 already
+# (links not pointing towards the wall).  Halfway bounce-back returns every
+# population that would leave the fluid, and the BGK collision keeps each
+# node's sum of f, so sum_i f_i over the fluid nodes is then conserved
+# exactly (to rounding).  Interpolating with the raw q, or taking the first
+# form with a solid x + c_i (whose f is zero), loses or creates f.
+
+def test_bounce_back_fallback_is_halfway_in_a_one_node_slit(oracle_lib):
+    nx, ny = 6, 9
+    shape = (nx, ny)
+    _, Y = np.meshgrid(np.arange(nx, dtype=float), np.arange(ny, dtype=float), indexing="ij")
+    dy = np.abs(Y - 4.2)
+    C1 = W.tanh_profile(np.minimum(dy, ny - dy) - 0.5)     # fluid: the row y = 4 only
+    assert (C1[:, 4] < 0.5).all() and (np.delete(C1, 4, axis=1) > 0.5).all()
+    o = O.Oracle(2, shape, W.kappas_for_angle(90.0), tau=0.8)
+    o.set_solid_field(W.flat(C1))
+    c, w = O.lattice(2)
+    fallback = 0
+    for x in range(nx):
+        n = x + nx * 4
+        for kdir in range(1, 9):
+            if c[kdir][1] == 0:
+                continue                       # along the slit: not cut
+            q = o.link_q(n, kdir)
+            assert 0.0 <= q <= 0.5 + 1e-12
+            fallback += q < 0.5 - 1e-9
+    assert fallback == 3 * nx                  # the three links towards y = 3
+    rng = np.random.default_rng(41)
+    Q, N = 9, nx * ny
+    fluid = W.flat(C1) < 0.5
+    fs = np.asarray(w)[:, None] * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, size=(Q, N))) * fluid
+    gs = np.zeros((Q, N))
+    gs[0] = 0.3 * fluid
+    o.set_postcollision(fs, gs)
+    s0 = fs[:, fluid].sum()
+    for _ in range(40):
+        o.step(1)
+        f, _ = o.get_populations()
+        assert f[:, fluid].sum() == pytest.approx(s0, rel=1e-13, abs=0)
+    # the populations moved (the check is not vacuous): across the slit they
+    # came back from the walls
+    f, _ = o.get_populations()
+    assert np.abs(f[:, fluid] - fs[:, fluid]).max() > 1e-3
+
+
 # --- two-step solid initialisation (Sec. II.B) -------------------------------
 
 def _sharp_mask(shape):
