@@ -163,3 +163,46 @@ def test_failed_solid_stage_blocks_the_liquid(gpu):
     sim.set_solid_field(f32(W.flat(C1)))
     sim.set_liquid(f32(W.flat(C2)))
     sim.step(5)
+
+
+CROP = (64, 64, 96)
+
+
+@pytest.mark.parametrize("storage,bar_c,bar_u", [(dsm.DSM_STORAGE_FP32, 1e-5, 1e-6),
+                                                 (dsm.DSM_STORAGE_FP16, 2e-3, 1e-4)])
+def test_pillar_crop_4x4_1000_fluid_steps(gpu, storage, bar_c, bar_u):
+    """The larger crop of the micropillar workload: 64 x 64 x 96 with 4 x 4
+    pillars (the full array's seed and jitter).  C1 from the GPU's solid
+    stage (5000 steps from the sharp mask at beta = 1e-3, Omega = 2e-4), the
+    liquid slab z in [44, 80) above the pillar tops, body force -1e-5 along
+    z; then 1000 fluid steps on the GPU and on the oracle from that same C1:
+    C2 and u at every node within the bars, liquid amount conserved."""
+    m = W.flat(W.pillar_mask(CROP))
+    solid = dsm.Simulation(3, CROP, KAPPA, gravity=GRAVITY, mask=m)
+    solid.init_solid(5000, 1e-3, 2e-4, 1.0, 1.0 / 6.0, dsm.DSM_SOLID_RESET)
+    C1 = solid.fields()["C1"]
+    solid.close()
+    z = np.meshgrid(*[np.arange(n, dtype=float) for n in CROP], indexing="ij")[2]
+    C2 = f32(W.flat(W.tanh_profile(W.periodic_slab_distance(z, 44.0, 80.0, CROP[2]))) * (1.0 - C1))
+    key = ("crop", CROP)
+    if key not in _ORACLE:
+        o = O.Oracle(3, CROP, KAPPA, gravity=GRAVITY, threads=16)
+        o.set_solid_field(C1)
+        o.set_liquid(C2)
+        o.step(1000)
+        _ORACLE[key] = {"C1": C1, "fields": o.fields(), "mass": o.mass()}
+        o.close()
+    ref = _ORACLE[key]
+    # the GPU's solid stage is deterministic: the FP16 run sees the same C1
+    assert np.array_equal(C1, ref["C1"])
+    sim = dsm.Simulation(3, CROP, KAPPA, gravity=GRAVITY, storage=storage, reduce_every=250)
+    sim.set_solid_field(C1)
+    sim.set_liquid(C2)
+    m0 = sim.mass()
+    sim.step(1000)
+    fl = sim.fields()
+    print(f"  solid nodes {int((C1 > 0.5).sum())} of {C1.size}; tiling {sim.tiling()}", flush=True)
+    assert report("C2 after 1000 fluid steps", fl["C2"], ref["fields"]["C2"]) < bar_c
+    assert report("u after 1000 fluid steps", fl["u"], ref["fields"]["u"]) < bar_u
+    assert abs(sim.mass()[1] - m0[1]) / m0[1] < 1e-9
+    assert abs(ref["mass"][1] - m0[1]) / m0[1] < 1e-9
