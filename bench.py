@@ -622,6 +622,13 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": measured_traffic("pillars", w.name, "", r32["tiling"]),
             "algorithmic_bytes": r32["alg_bytes"],
+            # the same count with every node charged as a fluid node (solid
+            # nodes' f traffic not skipped)
+            "without_solid_skip": {
+                "algorithmic_bytes": N * bytes_per_node(19, 4, False),
+                "achieved": round(N * bytes_per_node(19, 4, False) / (r32["fused_ms"] * 1e-3) / 1e9, 1),
+                "frac": round(N * bytes_per_node(19, 4, False) / (r32["fused_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            },
             "kernel": "k_step_fused<3,...> (one launch per step), 256x256x192 pillars, FP32",
             "stream_reference": stream_ref,
             "frac_of_best_copy": round(achieved / stream_ref["best_copy_GBps"], 4) if stream_ref else None,
