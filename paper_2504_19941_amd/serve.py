@@ -10,6 +10,11 @@ arrives while others run joins at the next quantum boundary; a quantum never
 runs past the step count any resident job asked for, so each job leaves at
 exactly its own step and its result is the one it would have alone.
 
+A job that fails (its set-up is rejected, or its lattice goes non-finite)
+is retired with its error, its arena slot freed, while the others go on:
+the lattices of a batch are independent, so its failure changes no other
+job's result.
+
 The scheduling logic (``Arena``, ``Server``, ``run_stream``) is plain host
 code; device work goes through an executor: ``GpuExecutor`` drives the C ABI,
 ``ModelExecutor`` replaces it with a timing model for host-only tests.
@@ -90,6 +95,7 @@ class Job:
     admitted: float | None = None
     finished: float | None = None
     result: dict | None = None
+    error: str | None = None  # set when the job failed (result stays None)
 
     @property
     def nodes(self) -> int:
@@ -118,6 +124,7 @@ class Server:
         self.queue = collections.deque()
         self.running = []
         self.done = []
+        self.failed = []
         self.changed = False
         self.rounds = 0
         self.steps_run = 0
@@ -145,10 +152,21 @@ class Server:
             self.queue.popleft()
             job.offset = off
             job.admitted = now
-            job.done_steps = self.ex.start(job, off)
+            try:
+                job.done_steps = self.ex.start(job, off)
+            except Exception as e:  # noqa: BLE001 (any set-up error fails this job only)
+                self.arena.free(off)
+                job.offset = None
+                self._retire_failed(job, f"{type(e).__name__}: {e}", now)
+                continue
             self.running.append(job)
             admitted.append(job)
         return admitted
+
+    def _retire_failed(self, job: Job, error: str, t: float):
+        job.error = error
+        job.finished = t
+        self.failed.append(job)
 
     def _rebuild(self):
         for off in self.table_blocks.values():
@@ -184,16 +202,23 @@ class Server:
         if self.changed:
             self._rebuild()
             self.changed = False
+        failed = {}
         if self.running:
             k = min(self.quantum, min(j.steps - j.done_steps for j in self.running))
             if k > 0:
-                self.ex.advance(k)
+                failed = self.ex.advance(k) or {}
                 self.steps_run += k
                 for j in self.running:
                     j.done_steps += k
         self.rounds += 1
-        finished = [j for j in self.running if j.done_steps >= j.steps]
         t = clock() if clock else now
+        for j in [j for j in self.running if j.id in failed]:
+            self.ex.drop(j)
+            self.arena.free(j.offset)
+            self.running.remove(j)
+            self._retire_failed(j, failed[j.id], t)
+            self.changed = True
+        finished = [j for j in self.running if j.done_steps >= j.steps]
         for j in finished:
             j.result = self.ex.finish(j)
             self.arena.free(j.offset)
@@ -230,11 +255,16 @@ def poisson_arrivals(count: int, rate: float, seed: int) -> list:
 
 
 def report(jobs, elapsed: float) -> dict:
+    """Latency and throughput over the jobs that finished; failed jobs are
+    counted apart."""
+    failed = [j for j in jobs if j.error is not None]
+    jobs = [j for j in jobs if j.error is None]
     lat = np.array([j.latency for j in jobs])
     wait = np.array([j.admitted - j.arrival for j in jobs])
     work = sum(j.nodes * j.steps for j in jobs)
     return {
         "jobs": len(jobs),
+        "failed_jobs": len(failed),
         "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
         "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
         "max_latency_s": round(float(lat.max()), 4),
@@ -250,11 +280,14 @@ class ModelExecutor:
     the caller (``now``), one quantum taking sum(nodes) / rate seconds per
     step plus a fixed overhead."""
 
-    def __init__(self, rate: float = 1e10, overhead: float = 1e-4, bytes_per_node: int = 400):
+    def __init__(self, rate: float = 1e10, overhead: float = 1e-4, bytes_per_node: int = 400,
+                 fail_start=(), fail_at=None):
         self.rate, self.overhead, self.bpn = rate, overhead, bytes_per_node
         self.t = 0.0
         self.resident = {}
         self.log = []
+        self.fail_start = set(fail_start)   # job ids whose set-up is rejected
+        self.fail_at = dict(fail_at or {})  # job id -> step at which it goes non-finite
 
     def now(self) -> float:
         return self.t
@@ -266,6 +299,8 @@ class ModelExecutor:
         return job.nodes * self.bpn + 4096
 
     def start(self, job, offset) -> int:
+        if job.id in self.fail_start:
+            raise RuntimeError(f"set-up of job {job.id} rejected")
         self.resident[job.id] = {"offset": offset, "steps": 1, "nodes": job.nodes}
         self.t += self.overhead
         return 1
@@ -279,12 +314,16 @@ class ModelExecutor:
     def rebuild(self, running, blocks):
         self.log.append(("rebuild", sorted(j.id for j in running)))
 
-    def advance(self, n: int):
-        for r in self.resident.values():
+    def advance(self, n: int) -> dict:
+        failed = {}
+        for jid, r in self.resident.items():
             r["steps"] += n
+            if jid in self.fail_at and r["steps"] >= self.fail_at[jid]:
+                failed[jid] = "non-finite values"
         nodes = sum(r["nodes"] for r in self.resident.values())
         self.log.append(("advance", n, sorted(self.resident)))
         self.t += self.overhead + n * nodes / self.rate
+        return failed
 
     def finish(self, job) -> dict:
         r = self.resident.pop(job.id)
@@ -311,6 +350,7 @@ class GpuExecutor:
         self.capacity = capacity
         self.sims = {}
         self.batches = {}
+        self.members = {}  # batch key -> job ids, in member order
         self.table_base = None
 
     def set_table_base(self, base: int):
@@ -332,9 +372,13 @@ class GpuExecutor:
         sim = self.dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
                                   gravity=w.gravity, storage=job.storage, device=self.device,
                                   dev_ptr=self.base + offset, rho=w.rho, tau_gas=w.tau_gas or 0.0)
-        sim.set_solid_field(f32(w.C1))
-        sim.set_liquid(f32(w.C2))
-        sim.step(1)  # the first step reads at-node populations; later steps run batched
+        try:
+            sim.set_solid_field(f32(w.C1))
+            sim.set_liquid(f32(w.C2))
+            sim.step(1)  # the first step reads at-node populations; later steps run batched
+        except Exception:
+            sim.close()
+            raise
         self.sims[job.id] = sim
         return 1
 
@@ -348,17 +392,34 @@ class GpuExecutor:
         for b in self.batches.values():
             b.close()
         self.batches = {}
-        groups = {}
+        self.members = {}
         for j in running:
-            groups.setdefault(j.storage, []).append(self.sims[j.id])
-        for key, sims in groups.items():
-            b = self.dsm.Batch(sims, device=self.device, dev_ptr=self.table_base + blocks[key])
+            self.members.setdefault(j.storage, []).append(j.id)
+        for key, ids in self.members.items():
+            b = self.dsm.Batch([self.sims[i] for i in ids], device=self.device,
+                               dev_ptr=self.table_base + blocks[key])
             b.tune()
             self.batches[key] = b
 
-    def advance(self, n: int):
-        for b in self.batches.values():
-            b.step(n)
+    def _unstable(self, jid) -> bool:
+        d = self.sims[jid].diagnostics()
+        return d["nonfinite_nodes"] > 0 or not np.isfinite(d["max_speed"]) or not np.all(np.isfinite(d["mass"]))
+
+    def advance(self, n: int) -> dict:
+        """n steps of every batch; returns {job id: error} of the jobs whose
+        lattice went non-finite (the batch's check names the failure, each
+        member's FP64 diagnostics say which; the others advanced normally)."""
+        failed = {}
+        for key, b in self.batches.items():
+            try:
+                b.step(n)
+            except self.dsm.DsmError as e:
+                if e.code != self.dsm.DSM_EUNSTABLE:
+                    raise
+                bad = [i for i in self.members[key] if self._unstable(i)] or list(self.members[key])
+                for i in bad:
+                    failed[i] = f"DSM_EUNSTABLE: {e}"
+        return failed
 
     def finish(self, job) -> dict:
         sim = self.sims.pop(job.id)

@@ -126,3 +126,32 @@ def test_served_jobs_match_the_oracle(gpu):
               f"max |dC2| vs oracle {err:.2e} (bar {bar:g})", flush=True)
         assert err < bar
     assert checked == {("duct", 0), ("particle", 0), ("duct", 1), ("particle", 1)}
+
+
+def test_a_job_that_goes_non_finite_is_retired_alone(gpu):
+    """One job of a served mix is driven non-finite (a body force of 50 on
+    its liquid); the batch step reports it, the job is retired with
+    DSM_EUNSTABLE and its slot freed, and every other job, including those
+    that shared its quanta, ends exactly as it does alone."""
+    import dataclasses
+
+    jobs = make_jobs(5, seed=57)
+    w = jobs[1].workload
+    bad = S.Job(99, dataclasses.replace(w, gravity=(50.0,) + tuple(w.gravity[1:])), 400,
+                storage=jobs[1].storage)
+    srv = S.make_gpu_server(512 << 20, quantum=10)
+    srv.submit(jobs[0], 0.0)
+    srv.submit(bad, 0.0)
+    for j in jobs[1:]:
+        srv.submit(j, 0.0)
+    rounds = 0
+    while srv.busy:
+        srv.step(float(rounds))
+        rounds += 1
+        assert rounds < 1000
+    print(f"  failed: {[(j.id, j.error) for j in srv.failed]}", flush=True)
+    assert [j.id for j in srv.failed] == [99]
+    assert "DSM_EUNSTABLE" in bad.error and bad.result is None and bad.done_steps < bad.steps
+    assert srv.arena.used == 0
+    assert len(srv.done) == len(jobs)
+    check_alone(jobs)

@@ -144,3 +144,29 @@ def test_batch_tables_that_do_not_fit_send_the_newest_job_back():
     while srv.busy:
         srv.step(1.0)
     assert all(j.result["steps"] == 12 for j in jobs)
+
+
+def test_failed_jobs_are_retired_and_the_others_finish():
+    """A job whose set-up is rejected and one whose lattice goes non-finite
+    in the middle of a quantum are retired with their errors and their arena
+    slots freed; every other job still runs exactly its steps, including the
+    ones that shared the failing quanta and the ones queued behind."""
+    ex = S.ModelExecutor(rate=1e9, overhead=1e-4, fail_start={3}, fail_at={5: 37})
+    srv = S.Server(ex, 100 << 20, quantum=10)  # room for three of these jobs at once
+    jobs = [job(k, (40, 40, 40), 60 + 5 * k) for k in range(10)]
+    arrivals = [0.0005 * k for k in range(10)]
+    elapsed = S.run_stream(srv, jobs, arrivals, clock=ex.now, sleep=ex.sleep)
+    bad = {3, 5}
+    assert sorted(j.id for j in srv.failed) == sorted(bad)
+    assert "rejected" in jobs[3].error and jobs[3].result is None and jobs[3].offset is None
+    assert "non-finite" in jobs[5].error and jobs[5].result is None
+    for j in jobs:
+        if j.id not in bad:
+            assert j.error is None and j.result["steps"] == j.steps
+    # job 5 failed inside a quantum that others shared, and later jobs ran
+    adv = [e for e in ex.log if e[0] == "advance"]
+    assert any(5 in e[2] and len(e[2]) > 1 for e in adv)
+    assert not any(5 in e[2] for e in adv[[k for k, e in enumerate(adv) if 5 in e[2]][-1] + 1:])
+    assert srv.arena.used == 0 and not srv.busy and not ex.resident
+    rep = S.report(jobs, elapsed)
+    assert rep["jobs"] == 8 and rep["failed_jobs"] == 2
