@@ -581,10 +581,17 @@ static void observe(dsmo_sim* s) {
 
 /* one step: moments, chemical potential, force, velocity and pressure,
  * collision, streaming (the order of the method in Sec. II.B) */
-static void one_step(dsmo_sim* s) {
+/* One step; DSMO_EUNSTABLE (the step not taken) if the state it starts from
+ * holds a non-finite C or u. */
+static int one_step(dsmo_sim* s) {
     observe(s);
+    long N = s->N;
+    for (long n = 0; n < N; ++n)
+        if (!isfinite(s->phi[n]) || !isfinite(s->u[n]) || !isfinite(s->u[N + n]) || !isfinite(s->u[2 * N + n]))
+            return DSMO_EUNSTABLE;
     stage_collide(s);
     stage_stream(s);
+    return DSMO_OK;
 }
 
 /* ------------------------------------------------------------------ */
@@ -620,7 +627,10 @@ int dsmo_init_solid(dsmo_sim* s, int n_steps, double beta, double omega, double 
         for (long n = 0; n < s->N; ++n) s->phi[n] = s->mask[n] ? 1.0 : 0.0;
         init_populations_from_phi(s);
     }
-    for (int t = 0; t < n_steps; ++t) one_step(s);
+    for (int t = 0; t < n_steps; ++t) {
+        int rc = one_step(s);
+        if (rc) return rc; /* C1 is not frozen from a non-finite state */
+    }
     stage_moment(s);
     memcpy(s->C1, s->phi, (size_t)s->N * sizeof(double));
     if (flags & DSMO_SOLID_REMASK)
@@ -652,7 +662,10 @@ int dsmo_set_gravity(dsmo_sim* s, const double g[3]) {
 int dsmo_step(dsmo_sim* s, int n) {
     if (!s || n < 0) return DSMO_EINVAL;
     if (s->stage != 2) return DSMO_ESTATE;
-    for (int t = 0; t < n; ++t) one_step(s);
+    for (int t = 0; t < n; ++t) {
+        int rc = one_step(s);
+        if (rc) return rc;
+    }
     return DSMO_OK;
 }
 

@@ -32,6 +32,7 @@ enum {
     DSMO_OK = 0,
     DSMO_EINVAL = -1,
     DSMO_ENOMEM = -2,
+    DSMO_EUNSTABLE = -4,
     DSMO_ESTATE = -5
 };
 
@@ -78,7 +79,8 @@ int  dsmo_num_directions(const dsmo_sim* s);
 /* Solid stage (Sec. II.B, solid relaxation).  flags: RESET starts from the
  * sharp indicator C1 = 1[S]; otherwise the live solid-stage state continues.
  * REMASK replaces S by {C1 > 1/2} after the run.  C1 is frozen to the sum of
- * the solid-stage g populations when the call returns. */
+ * the solid-stage g populations when the call returns, unless a step meets
+ * a non-finite state (DSMO_EUNSTABLE, nothing frozen). */
 int  dsmo_init_solid(dsmo_sim* s, int n_steps, double beta, double omega,
                      double tau_s, double mobility_s, int flags);
 /* Alternative to the solid stage: an externally given diffuse C1. */
@@ -86,7 +88,9 @@ int  dsmo_set_solid_field(dsmo_sim* s, const double* C1);
 /* Liquid initial condition: f = 0, g = g_eq(C2, mu(C2), u = 0). */
 int  dsmo_set_liquid(dsmo_sim* s, const double* C2);
 int  dsmo_set_gravity(dsmo_sim* s, const double g[3]);
-/* n fluid-stage steps. */
+/* n fluid-stage steps.  DSMO_EUNSTABLE when a step starts from a state whose
+ * order parameter or velocity is not finite at some node (that step is not
+ * taken; the state is left as computed). */
 int  dsmo_step(dsmo_sim* s, int n);
 
 /* Observables of the current state. */

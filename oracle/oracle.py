@@ -17,6 +17,7 @@ FORCE_POTENTIAL = 0
 FORCE_AS_TYPESET = 1
 SOLID_RESET = 1
 SOLID_REMASK = 2
+EUNSTABLE = -4  # a step met a non-finite C or u
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -82,9 +83,15 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+class OracleError(RuntimeError):
+    def __init__(self, rc, what):
+        super().__init__(f"oracle {what} failed with code {rc}")
+        self.code = rc
+
+
 def _check(rc, what):
     if rc != 0:
-        raise RuntimeError(f"oracle {what} failed with code {rc}")
+        raise OracleError(rc, what)
 
 
 def lattice(dim):

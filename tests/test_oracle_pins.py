@@ -549,3 +549,25 @@ def test_young_history_matches_current_oracle(oracle_lib):
     assert th == pytest.approx(g["history"][0]["theta"], abs=1e-9)
     F, E = o.free_energy()
     assert F == pytest.approx(g["history"][0]["F"], rel=1e-12)
+
+
+def test_oracle_reports_a_state_that_went_non_finite(oracle_lib):
+    """Failure detection on the CPU: a body force far beyond the scheme's
+    range drives the drop's velocity non-finite; the oracle then refuses the
+    next step with EUNSTABLE and leaves the state as computed, while the same
+    drop under a small force steps on."""
+    w = W.config_2d_contact_angle(90.0)
+    for g, unstable in ((1e-5, False), (50.0, True)):
+        o = O.Oracle(2, w.shape, w.kappa, mobility=w.mobility, tau=w.tau, gravity=(g, 0.0, 0.0), threads=4)
+        o.set_solid_field(W.flat(w.C1))
+        o.set_liquid(W.flat(w.C2))
+        if not unstable:
+            o.step(50)
+            assert np.isfinite(o.fields()["u"]).all()
+            continue
+        with pytest.raises(O.OracleError) as e:
+            o.step(200)
+        assert e.value.code == O.EUNSTABLE
+        assert not np.isfinite(o.fields()["u"]).all()
+        with pytest.raises(O.OracleError):
+            o.step(1)
