@@ -7,9 +7,9 @@
  * It walks both lattices, both stages, the two-step solid initialisation,
  * the density/viscosity contrast, both readings of the confining potential
  * and of the surface-tension force, population get/set and the
- * post-collision entry, the observables, the wall fraction of every link
- * and the argument checks, and exits non-zero if an invariant of the scheme
- * fails (the liquid amount is conserved by every fluid step; the solid
+ * post-collision entry, the observables, the wall fraction of every link,
+ * the argument checks and the refusal of a non-finite state, and exits
+ * non-zero if an invariant of the scheme fails (the liquid amount is conserved by every fluid step; the solid
  * amount by every solid step).
  */
 #include <math.h>
@@ -157,6 +157,44 @@ static void run_case(int dim, const int n[3], int contrast, int force_reading, i
     free(S);
 }
 
+/* a body force far beyond the scheme's range: the oracle refuses the step
+ * that starts from the non-finite state, and again after that */
+static void unstable_case(const int n[3]) {
+    dsmo_params p;
+    memset(&p, 0, sizeof(p));
+    p.dim = 2;
+    p.nx = n[0];
+    p.ny = n[1];
+    p.nz = 1;
+    p.kappa[0] = 0.01;
+    p.kappa[1] = 0.006;
+    p.kappa[2] = 0.009;
+    p.alpha = 1.0;
+    p.tau = 1.0;
+    p.mobility = 0.1;
+    p.gravity[0] = 50.0;
+    p.threads = 2;
+    p.rho_liquid = 1.0;
+    p.rho_gas = 1.0;
+    p.tau_gas = 1.0;
+    long N = (long)p.nx * p.ny;
+    double* C1 = malloc(N * sizeof(double));
+    double* C2 = malloc(N * sizeof(double));
+    unsigned char* mask = malloc(N);
+    geometry(2, n, C1, C2, mask);
+    dsmo_sim* s = NULL;
+    CHECK(dsmo_create(&p, mask, &s) == DSMO_OK, "create (unstable case)");
+    if (s) {
+        CHECK(dsmo_set_solid_field(s, C1) == DSMO_OK && dsmo_set_liquid(s, C2) == DSMO_OK, "set (unstable)");
+        CHECK(dsmo_step(s, 500) == DSMO_EUNSTABLE, "step under a body force of 50");
+        CHECK(dsmo_step(s, 1) == DSMO_EUNSTABLE, "step after the state went non-finite");
+        dsmo_destroy(s);
+    }
+    free(C1);
+    free(C2);
+    free(mask);
+}
+
 int main(void) {
     const int n2[3] = {20, 14, 1}, n3[3] = {12, 9, 10};
     dsmo_params bad;
@@ -169,6 +207,7 @@ int main(void) {
             run_case(2, n2, contrast, fr, contrast);
             run_case(3, n3, contrast, fr, 1 - contrast);
         }
+    unstable_case(n2);
     if (failures) {
         fprintf(stderr, "%d checks failed\n", failures);
         return 1;
