@@ -159,7 +159,7 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-def run_storage(dsm, W, w, dev, storage, args, fluid_nodes, solid_nodes):
+def run_storage(dsm, W, w, dev, storage, args, fluid_nodes, solid_nodes, tune_tiling=False):
     """Times the step for one population storage mode: timed region 1 is K
     whole steps bracketed by events (throughput), timed region 2 the same with
     HIP events around every launch (per-launch kernel duration)."""
@@ -188,6 +188,12 @@ def run_storage(dsm, W, w, dev, storage, args, fluid_nodes, solid_nodes):
     fused_ms, links_ms = sim.step_timed(args.steps)
     m1 = sim.mass()
     tiling = sim.tiling()
+    tuned = None
+    if tune_tiling:
+        # the measured tiling tuner on the same lattice, beside the default
+        v, planes, tms = sim.tune_tiling(reps=3)
+        tuned = {"tiling": [v, planes], "fused_kernel_us": round(tms * 1e3, 2),
+                 "default_tiling": list(tiling), "default_fused_kernel_us": round(fused_ms * 1e3, 2)}
     sim.close()
     pop_bytes = 2 if storage == dsm.DSM_STORAGE_FP16 else 4
     alg = bytes_per_launch(19 if w.dim == 3 else 9, pop_bytes, fluid_nodes, solid_nodes)
@@ -201,6 +207,7 @@ def run_storage(dsm, W, w, dev, storage, args, fluid_nodes, solid_nodes):
         "achieved": alg / (fused_ms * 1e-3) / 1e9,
         "drift": abs(m1[1] - m0[1]) / abs(m0[1]),
         "tiling": tiling,
+        "tuned": tuned,
     }
 
 
@@ -540,14 +547,14 @@ def main():
                 "fused_kernel_us": round(r["fused_ms"] * 1e3, 2), "link_kernel_us": round(r["links_ms"] * 1e3, 2),
                 "hbm_GBps": round(r["achieved"], 1), "hbm_frac": round(r["achieved"] / HBM_PEAK_GBPS, 4),
                 "algorithmic_bytes": r["alg_bytes"], "tiling": list(r["tiling"]),
-                "liquid_mass_drift_rel": r["drift"]}
+                "liquid_mass_drift_rel": r["drift"], **({"tiling_tuner": r["tuned"]} if r["tuned"] else {})}
 
     # headline: the micropillar lattice, FP32 and FP16 storage
     w, solid_s = pillar_workload(dsm, W, dev)
     solid_nodes = int((np.asarray(w.C1, dtype=np.float32) > 0.5).sum())
     fluid_nodes = w.nodes - solid_nodes
-    r32 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP32, args, fluid_nodes, solid_nodes)
-    r16 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP16, args, fluid_nodes, solid_nodes)
+    r32 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP32, args, fluid_nodes, solid_nodes, tune_tiling=True)
+    r16 = run_storage(dsm, W, w, dev, dsm.DSM_STORAGE_FP16, args, fluid_nodes, solid_nodes, tune_tiling=True)
     print(f"bench.py: {w.name}: fp32 {r32['mlups']:.0f} MLUPS, fp16 {r16['mlups']:.0f} MLUPS",
           file=sys.stderr, flush=True)
 
@@ -632,6 +639,7 @@ def main():
             "kernel": "k_step_fused<3,...> (one launch per step), 256x256x192 pillars, FP32",
             "stream_reference": stream_ref,
             "frac_of_best_copy": round(achieved / stream_ref["best_copy_GBps"], 4) if stream_ref else None,
+            "tiling_tuner": r32["tuned"],
         },
     }
     out["fp16_store"] = storage_block(r16, N)

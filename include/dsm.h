@@ -276,6 +276,18 @@ int dsm_set_tiling(dsm_sim* s, int variant, int planes);
 int dsm_get_tiling(const dsm_sim* s, int* variant, int* planes);
 int dsm_tiling_variants(int dim);
 
+/* Measured tiling tuner: times every tile variant with each march of 8, 16,
+ * 32, 48, 64, 96 and 128 planes (3D) or 4, 8, 16, 32, 64 and 128 (2D),
+ * marches of Z planes or more timed once, on the lattice itself (one
+ * untimed step, then reps steps timed as dsm_step_timed times them) and
+ * installs the fastest.  Results do not depend on the tiling; the lattice
+ * advances by 1 + reps steps per candidate (dsm_step_count tells how many).
+ * *ms_per_step (may be NULL) receives the fused kernel's time per step under
+ * the chosen tiling.  Fluid stage, fused kernel only; reps in [1, 1000].  On
+ * an error the previous tiling is restored.  Errors: DSM_EINVAL, DSM_ESTATE,
+ * DSM_EUNSTABLE, DSM_EDEVICE. */
+int dsm_tune_tiling(dsm_sim* s, int reps, double* ms_per_step);
+
 /* Releases the host handle (the device buffer stays the caller's). */
 int dsm_destroy(dsm_sim* s);
 

@@ -882,6 +882,45 @@ int dsm_get_tiling(const dsm_sim* s, int* variant, int* planes) {
 
 int dsm_tiling_variants(int dim) { return (dim == 2 || dim == 3) ? fused_tile_variants(dim) : 0; }
 
+int dsm_tune_tiling(dsm_sim* s, int reps, double* ms_per_step) {
+    if (!s) return fail(DSM_EINVAL, "sim is NULL");
+    if (reps < 1 || reps > 1000) return fail(DSM_EINVAL, "reps must be in [1, 1000]");
+    if (s->stage != 2) return fail(DSM_ESTATE, "dsm_tune_tiling needs a liquid (dsm_set_liquid) first");
+    if (s->p.kernel != DSM_KERNEL_FUSED) return fail(DSM_EINVAL, "dsm_tune_tiling tunes the fused kernel only");
+    static const int kPlanes3[] = {8, 16, 32, 48, 64, 96, 128};
+    static const int kPlanes2[] = {4, 8, 16, 32, 64, 128};
+    const int dim = s->p.dim, Z = s->geom.Z;
+    const int* list = dim == 3 ? kPlanes3 : kPlanes2;
+    const int count = dim == 3 ? (int)(sizeof(kPlanes3) / sizeof(int)) : (int)(sizeof(kPlanes2) / sizeof(int));
+    const int v0 = s->tile_variant, p0 = s->tile_planes;
+    int bv = v0, bp = p0;
+    double best = 1e300;
+    for (int v = 0; v < fused_tile_variants(dim); ++v)
+        for (int k = 0; k < count; ++k) {
+            // marches of at least Z planes are one and the same launch: time the first only
+            if (k > 0 && list[k - 1] >= Z) break;
+            s->tile_variant = v;
+            s->tile_planes = list[k];
+            int rc = dsm_step(s, 1);
+            double ms = 0.0;
+            if (!rc) rc = dsm_step_timed(s, reps, &ms, nullptr);
+            if (rc) {
+                s->tile_variant = v0;
+                s->tile_planes = p0;
+                return rc;
+            }
+            if (ms < best) {
+                best = ms;
+                bv = v;
+                bp = list[k];
+            }
+        }
+    s->tile_variant = bv;
+    s->tile_planes = bp;
+    if (ms_per_step) *ms_per_step = best;
+    return DSM_OK;
+}
+
 int dsm_destroy(dsm_sim* s) {
     if (!s) return fail(DSM_EINVAL, "sim is NULL");
     hipError_t e = hipStreamSynchronize(s->stream);

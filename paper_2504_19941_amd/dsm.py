@@ -27,7 +27,7 @@ EXPORTED = [
     "dsm_set_gravity", "dsm_step", "dsm_step_timed", "dsm_free_energy", "dsm_mass", "dsm_diagnostics",
     "dsm_diagnostics_noalloc", "dsm_solid_region", "dsm_fields", "dsm_chemical_potential", "dsm_get_populations", "dsm_set_populations", "dsm_set_postcollision",
     "dsm_state_bytes", "dsm_get_state", "dsm_set_state", "dsm_step_count", "dsm_set_tiling",
-    "dsm_get_tiling", "dsm_tiling_variants", "dsm_destroy", "dsm_last_error",
+    "dsm_get_tiling", "dsm_tiling_variants", "dsm_tune_tiling", "dsm_destroy", "dsm_last_error",
     "dsm_batch_required_bytes", "dsm_batch_create", "dsm_batch_set_schedule", "dsm_batch_get_schedule",
     "dsm_batch_tune", "dsm_batch_step", "dsm_batch_step_timed", "dsm_batch_size", "dsm_batch_items",
     "dsm_batch_destroy",
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.dsm_set_tiling.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.dsm_get_tiling.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.dsm_tiling_variants.argtypes = [ctypes.c_int]
+    lib.dsm_tune_tiling.argtypes = [vp, ctypes.c_int, _dp]
     lib.dsm_destroy.argtypes = [vp]
     lib.dsm_last_error.argtypes = []
     lib.dsm_last_error.restype = ctypes.c_char_p
@@ -305,6 +306,15 @@ def dsm_get_tiling(h):
     return v.value, p.value
 
 
+def dsm_tune_tiling(h, reps=3) -> float:
+    """Times every tile variant and march on the lattice itself (it advances
+    by 1 + reps steps per candidate), installs the fastest; returns the fused
+    kernel's ms per step under it."""
+    ms = ctypes.c_double(0.0)
+    _check(load().dsm_tune_tiling(h, int(reps), ctypes.byref(ms)), "dsm_tune_tiling")
+    return ms.value
+
+
 def dsm_tiling_variants(dim) -> int:
     return int(load().dsm_tiling_variants(int(dim)))
 
@@ -480,6 +490,11 @@ class Simulation:
     def tiling(self):
         """(variant, planes) of the fused step's launch shape in use."""
         return dsm_get_tiling(self.handle)
+
+    def tune_tiling(self, reps=3):
+        """Measured tiling tuner (dsm_tune_tiling): returns (variant, planes, ms)."""
+        ms = dsm_tune_tiling(self.handle, reps)
+        return (*self.tiling(), ms)
 
     @property
     def steps(self) -> int:

@@ -113,6 +113,7 @@ int main(void) {
     CHECK(dsm_step_count(NULL) < 0, "step_count");
     CHECK(dsm_set_tiling(NULL, 0, 16) == DSM_EINVAL, "set_tiling");
     CHECK(dsm_get_tiling(NULL, &v, &pl) == DSM_EINVAL, "get_tiling");
+    CHECK(dsm_tune_tiling(NULL, 3, &F) == DSM_EINVAL, "tune_tiling");
     CHECK(dsm_tiling_variants(3) >= 1 && dsm_tiling_variants(2) >= 1 && dsm_tiling_variants(5) == 0, "variants");
     CHECK(dsm_destroy(NULL) == DSM_EINVAL, "destroy");
     /* batch calls */

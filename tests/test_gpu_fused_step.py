@@ -134,6 +134,34 @@ def test_launch_shape_does_not_change_results(gpu, dim):
             assert st == ref, f"variant {variant} planes {planes} differs"
 
 
+@pytest.mark.parametrize("dim,shape", [(2, (300, 120)), (3, (96, 40, 50))])
+def test_measured_tiling_tuner(gpu, dim, shape):
+    """dsm_tune_tiling times every variant and march on the lattice itself,
+    installs one of them, and leaves the state where the same number of
+    plain steps leaves it (the tiling changes no result)."""
+    mask, C1, C2 = wall_and_particle(dim, shape, seed=73)
+    sims = []
+    for _ in range(2):
+        sim = dsm.Simulation(dim, shape, KAPPA, gravity=(1e-5, 0.0, 0.0))
+        sim.set_solid_field(W.flat(C1))
+        sim.set_liquid(W.flat(C2))
+        sims.append(sim)
+    tuned, plain = sims
+    v, planes, ms = tuned.tune_tiling(reps=2)
+    taken = tuned.steps
+    print(f"  tuned tiling ({v}, {planes}), fused kernel {ms * 1e3:.1f} us, {taken} steps taken", flush=True)
+    assert 0 <= v < dsm.dsm_tiling_variants(dim) and planes >= 1 and ms > 0.0
+    assert tuned.tiling() == (v, planes)
+    assert taken >= dsm.dsm_tiling_variants(dim) * 3
+    plain.step(taken)
+    assert tuned.get_state() == plain.get_state()
+    tuned.step(5)
+    plain.step(5)
+    assert tuned.get_state() == plain.get_state()
+    with pytest.raises(dsm.DsmError):
+        dsm.dsm_tune_tiling(tuned.handle, 0)
+
+
 def test_checkpoint_resume_is_bitwise(gpu):
     shape = (48, 20, 24)
     mask, C1, C2 = wall_and_particle(3, shape, seed=81)
