@@ -44,6 +44,7 @@ METRIC = "MLUPS and HBM GB/s (% peak), FP32 vs FP16-store; p50/p99 job latency"
 PMC_SUMMARY = {
     "pillars": os.path.join(ROOT, "profiles", "fused_step_d3q19_256x256x192_pillars_pmc.md"),
     "sessile": os.path.join(ROOT, "profiles", "fused_step_d3q19_128cube_pmc.md"),
+    "batch": os.path.join(ROOT, "profiles", "batch_step_d2q9_512_lattices_pmc.md"),
 }
 KERNEL_SOURCES = ["dsm_fused.hip", "dsm_lattice.h", "dsm_internal.h"]
 
@@ -284,6 +285,8 @@ def run_batch(dsm, W, dev, args):
         "hbm_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
         "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes": alg,
+        "traffic": measured_traffic("batch", "d2q9-512-sinusoid-batch", "",
+                                    (batch.schedule(2)["variant"], batch.schedule(2)["planes"])),
         "schedule": batch.schedule(2),
         "tuner": "measured (every candidate timed on the batch itself, 5 steps each)",
         "tune_s": round(mtune_s, 3),
