@@ -224,6 +224,10 @@ struct F16 {  // FP16 holding value * kHalfScale
     }
 };
 
+// Lane offset past every plane: a buffer load there returns 0 without memory
+// traffic.
+constexpr unsigned kOOBLoad = 0x80000000u;  // (the pipelined tile names it kOOB)
+
 // One tile of the march: columns [x0, x0 + 64 TXW) x rows [y0, y0 + TY),
 // planes [z0, z0 + TZ) of one lattice.
 template <int D, int TXW, int TY, int STAGE, bool PULL, bool RHO, typename E>
@@ -255,6 +259,13 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
     const int x = x0 + xseg * 64 + lane;
     const int y = y0 + yrow;  // uniform
     const bool active = (x < X) && (y < Y);
+    // Lanes past the lattice's last column or row pull no g, except the first
+    // one (column X, row Y): it holds C of the wrapped column (row) that the
+    // last real one's stencil reads.  The others' ring cells are read by no
+    // lattice node; their g pulls go past the plane and return 0 without
+    // memory traffic (their rest value and C1 are still read: 12 of 84 bytes,
+    // through plain loads that stay unconditional).
+    const bool pulls = x <= X && y <= Y;
     const int rint = (1 + xseg * 64 + lane) + CRX * (HY + yrow);  // own region index
     // Region indices of the columns x - 1, x, x + 1 in the own row.  A tile
     // that spans its whole lattice row (x0 == 0, X <= TX) wraps them onto its
@@ -266,10 +277,14 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Phys& ph, const 
     const int rrow = CRX * (HY + yrow);
     const int rcol[3] = {full_row ? 1 + pmod(xl - 1, X) : xl, xl + 1, full_row ? 1 + pmod(xl + 1, X) : xl + 2};
 
-    // Own column, wrapped (lanes beyond the lattice edge of a ragged tile
-    // compute C of the wrapped column: the last real column needs it).
+    // Own column, wrapped (the first lane past the edge of a ragged tile
+    // computes C of the wrapped column, which the last real column reads).
     const int xv[3] = {pmod(x - 1, X), pmod(x, X), pmod(x + 1, X)};   // x-1, x, x+1
-    const unsigned xb[3] = {ES * xv[0], ES * xv[1], ES * xv[2]};         // as byte offsets
+    // as byte offsets; past the plane for a lane that pulls nothing (every
+    // other access of such a lane is masked already: it stores nothing and
+    // pulls no f)
+    const unsigned xb[3] = {pulls ? ES * xv[0] : kOOBLoad, pulls ? ES * xv[1] : kOOBLoad,
+                            pulls ? ES * xv[2] : kOOBLoad};
     const int yw = pmod(y, Y);
     const int yv[3] = {yw == 0 ? Y - 1 : yw - 1, yw, yw + 1 == Y ? 0 : yw + 1};
 
@@ -603,6 +618,13 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
     const int x = x0 + xseg * 64 + lane;
     const int y = y0 + yrow;  // uniform
     const bool active = (x < X) && (y < Y);
+    // Lanes past the lattice's last column or row pull no g, except the first
+    // one (column X, row Y): it holds C of the wrapped column (row) that the
+    // last real one's stencil reads.  The others' ring cells are read by no
+    // lattice node; their g pulls go past the plane and return 0 without
+    // memory traffic (their rest value and C1 are still read: 12 of 84 bytes,
+    // through plain loads that stay unconditional).
+    const bool pulls = x <= X && y <= Y;
     const int rint = (1 + xseg * 64 + lane) + CRX * (HY + yrow);  // own region index
     // Region indices of the columns x - 1, x, x + 1 in the own row.  A tile
     // that spans its whole lattice row (x0 == 0, X <= TX) wraps them onto its
@@ -615,7 +637,9 @@ __device__ __forceinline__ void fused_tile_pipe(const Geom& g, const Phys& ph, c
     const int rcol[3] = {full_row ? 1 + pmod(xl - 1, X) : xl, xl + 1, full_row ? 1 + pmod(xl + 1, X) : xl + 2};
 
     const int xv[3] = {pmod(x - 1, X), pmod(x, X), pmod(x + 1, X)};  // x-1, x, x+1
-    const unsigned xb[3] = {ES * xv[0], ES * xv[1], ES * xv[2]};        // as byte offsets
+    // as byte offsets; past the plane for a lane that pulls nothing (every
+    // other access of such a lane is masked already)
+    const unsigned xb[3] = {pulls ? ES * xv[0] : kOOB, pulls ? ES * xv[1] : kOOB, pulls ? ES * xv[2] : kOOB};
     const int yw = pmod(y, Y);
     const int yv[3] = {yw == 0 ? Y - 1 : yw - 1, yw, yw + 1 == Y ? 0 : yw + 1};
 
