@@ -107,7 +107,11 @@ size_t dsm_required_bytes(const dsm_params* p);
  * region the confining potential holds the solid to), kappa_m and alpha
  * (Sec. II.A), tau and M (Sec. II.B), body force.
  *   mask      host, N bytes, 1 where the node lies in S (may be NULL: S empty).
- *             The solid starts as the sharp indicator C1 = 1[S].
+ *             The solid starts as the sharp indicator C1 = 1[S], with the
+ *             cut links of interpolated bounce-back (Sec. II.B) built from
+ *             it, so a liquid may be set on it without a solid stage (if
+ *             they overflow the table, dsm_set_liquid returns DSM_ESTATE
+ *             until a solid stage or dsm_set_solid_field succeeds).
  *   dev_buf   device pointer to dev_bytes >= dsm_required_bytes(p) bytes,
  *             256-byte aligned, owned by the caller.
  *   stream    hipStream_t (NULL = default stream) for all device work.

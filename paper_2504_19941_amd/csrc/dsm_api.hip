@@ -508,6 +508,14 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     if (e == hipSuccess) e = hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return cleanup(fail(DSM_EDEVICE, std::string("dsm_create: ") + hipGetErrorString(e)));
+    // The sharp solid is a solid of the fluid stage like any other: a liquid
+    // may be set on it at once, and its cut links (wall fractions from
+    // C1 = 1[S]) are then those the split kernels evaluate on the fly.  A
+    // mask with more cut links than the table holds needs a solid stage (or
+    // a solid field) before a liquid.
+    const int rc = build_links(s);
+    if (rc == DSM_EDEVICE) return cleanup(rc);
+    s->solid_failed = rc != DSM_OK;
     *out = s;
     return DSM_OK;
 }
@@ -758,6 +766,10 @@ int dsm_get_populations(dsm_sim* s, double* f, double* g) {
 }
 
 static int upload_pops(dsm_sim* s, const double* f, const double* g, int pair) {
+    // a fluid state needs the cut links of a solid that was set successfully
+    // (a failed solid stage leaves the handle in the solid stage)
+    if (s->solid_failed && s->stage != 1)
+        return fail(DSM_ESTATE, "the last solid stage or solid field failed; set the solid again first");
     int rc = upload_pops_one(s, f, s->d.f[pair], false);
     if (!rc) rc = upload_pops_one(s, g, s->d.g[pair], true);
     if (!rc) rc = clear_spare_f(s, 1 - pair);

@@ -45,6 +45,29 @@ def test_fluid_stage(oracle_lib, dim, shape):
 
 
 @pytest.mark.parametrize("dim,shape", CASES)
+def test_fluid_stage_on_the_sharp_mask(oracle_lib, dim, shape):
+    """A liquid set right after creation, on the sharp solid C1 = 1[S] (no
+    solid stage): bounce-back with the wall fractions of the sharp field."""
+    mask, _, _ = wall_and_particle(dim, shape, thickness=2, radius=2.5, seed=8)
+    C1 = mask.astype(np.float64)
+    C2 = W.drop_field(shape, [0.7 * n for n in shape[:-1]] + [1.5], 0.3 * min(shape), C1, open_axis=dim - 1)
+    k = W.kappas_for_angle(70.0)
+    grav = (1e-4, -2e-4, 3e-4)[:dim] + (0.0,) * (3 - dim)
+    o = Oracle(dim, shape, k, gravity=grav, mask=W.flat(mask))
+    m = MiniOracle(dim, shape, k, gravity=grav, mask=mask)
+    o.set_liquid(W.flat(C2))
+    m.set_liquid(C2)
+    o.step(100)
+    m.step(100)
+    fo, fm = o.fields(), m.fields()
+    assert np.array_equal(fo["C1"], W.flat(C1))
+    for key in ("C2", "p"):
+        assert np.abs(fo[key] - fm[key]).max() < 1e-13
+    assert np.abs(fo["u"] - fm["u"]).max() < 1e-13
+    assert np.abs(fo["u"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("dim,shape", CASES)
 def test_solid_stage(oracle_lib, dim, shape):
     mask, _, _ = wall_and_particle(dim, shape, thickness=2, radius=2.5, seed=4)
     k = W.kappas_for_angle(90.0)
