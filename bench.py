@@ -346,10 +346,11 @@ def run_serve(dsm, W, dev, args, plain_mlups):
         sim = dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
                              gravity=w.gravity, storage=j.storage, rho=w.rho, tau_gas=w.tau_gas or 0.0,
                              device=dev)
-        sim.set_solid_field(f32(W.flat(w.C1)))
-        sim.set_liquid(f32(W.flat(w.C2)))
+        sim.set_solid_field(W.flat(w.C1))
+        sim.set_liquid(W.flat(w.C2))
         sim.step(j.steps)
-        sim.fields()
+        sim.diagnostics()
+        sim.fields(("C2",))
         alone = time.perf_counter() - t0
         sim.close()
         slow.append(j.latency / alone)

@@ -196,7 +196,9 @@ int dsm_mass(dsm_sim* s, double m[3]);
  * u (dim planes; rho u = sum_i c_i f_i + F/2, Sec. II.B) and the pressure
  * P = p~ / 3, where p~ = sum_i f_i + u . grad(rho) / 2 is the zeroth moment
  * of f (Sec. II.B).  Solid nodes report u = 0 and P = 0.  Any pointer may be
- * NULL.  Errors: DSM_EINVAL, DSM_ESTATE, DSM_EDEVICE. */
+ * NULL; only the requested outputs are computed and copied (u and P need a
+ * pass of the velocity kernels, C1 and C2 one device-to-host copy each, C3
+ * both copies).  Errors: DSM_EINVAL, DSM_ESTATE, DSM_EDEVICE. */
 int dsm_fields(dsm_sim* s, double* C1, double* C2, double* C3, double* u, double* p);
 
 /* Global diagnostics of the current state, from one FP64 reduction over

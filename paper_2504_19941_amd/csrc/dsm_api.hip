@@ -513,9 +513,11 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
     // C1 = 1[S]) are then those the split kernels evaluate on the fly.  A
     // mask with more cut links than the table holds needs a solid stage (or
     // a solid field) before a liquid.
-    const int rc = build_links(s);
-    if (rc == DSM_EDEVICE) return cleanup(rc);
-    s->solid_failed = rc != DSM_OK;
+    if (mask) {
+        const int rc = build_links(s);
+        if (rc == DSM_EDEVICE) return cleanup(rc);
+        s->solid_failed = rc != DSM_OK;
+    }
     *out = s;
     return DSM_OK;
 }
@@ -711,18 +713,31 @@ int dsm_diagnostics(dsm_sim* s, dsm_diag* out) {
 int dsm_fields(dsm_sim* s, double* C1, double* C2, double* C3, double* u, double* p) {
     if (!s) return fail(DSM_EINVAL, "sim is NULL");
     if (s->stage == 0) return fail(DSM_ESTATE, "no live state");
-    int rc = observe(s);
+    // only what is asked for: the velocity and pressure kernels run when u or
+    // p is requested, and each concentration plane is copied when an output
+    // needs it (C3 needs both)
+    int rc = DSM_OK;
+    if (u || p) {
+        rc = observe(s);
+    } else {
+        const hipError_t e = launch_moment(s->p.dim, s->geom, PG(s, s->cur), s->d.phi, s->pull, s->stream);
+        if (e != hipSuccess) rc = fail(DSM_EDEVICE, std::string("dsm_fields: ") + hipGetErrorString(e));
+    }
     if (rc) return rc;
     const size_t N = (size_t)s->N;
-    std::vector<double> c1(N), phi(N);
-    rc = download_field(s, s->stage == 2 ? s->d.c1 : s->d.phi, c1.data(), N);
-    if (rc) return rc;
-    if (s->stage == 2) {
+    const bool fluid = s->stage == 2;
+    const bool need_c1 = C1 || C3, need_phi = fluid && (C2 || C3);
+    std::vector<double> c1(need_c1 ? N : 0), phi(need_phi ? N : 0);
+    if (need_c1) {
+        rc = download_field(s, fluid ? s->d.c1 : s->d.phi, c1.data(), N);
+        if (rc) return rc;
+    }
+    if (need_phi) {
         rc = download_field(s, s->d.phi, phi.data(), N);
         if (rc) return rc;
     }
     for (size_t n = 0; n < N; ++n) {
-        double a = c1[n], b = s->stage == 2 ? phi[n] : 0.0;
+        const double a = need_c1 ? c1[n] : 0.0, b = need_phi ? phi[n] : 0.0;
         if (C1) C1[n] = a;
         if (C2) C2[n] = b;
         if (C3) C3[n] = 1.0 - a - b;

@@ -246,11 +246,21 @@ def dsm_solid_region(h, N):
     return m
 
 
-def dsm_fields(h, N, dim):
-    C1, C2, C3, p = (np.zeros(N) for _ in range(4))
-    u = np.zeros(dim * N)
-    _check(load().dsm_fields(h, _p(C1), _p(C2), _p(C3), _p(u), _p(p)), "dsm_fields")
-    return {"C1": C1, "C2": C2, "C3": C3, "u": u.reshape(dim, N), "p": p}
+FIELDS = ("C1", "C2", "C3", "u", "p")
+
+
+def dsm_fields(h, N, dim, which=FIELDS):
+    """The requested fields (names from FIELDS) as FP64 host arrays; the
+    library computes and copies only those."""
+    bad = set(which) - set(FIELDS)
+    if bad:
+        raise ValueError(f"unknown fields {sorted(bad)}")
+    out = {k: np.zeros(dim * N if k == "u" else N) for k in FIELDS if k in which}
+    ptr = [_p(out[k]) if k in out else None for k in FIELDS]
+    _check(load().dsm_fields(h, *ptr), "dsm_fields")
+    if "u" in out:
+        out["u"] = out["u"].reshape(dim, N)
+    return out
 
 
 def dsm_chemical_potential(h, N):
@@ -457,8 +467,8 @@ class Simulation:
     def mass(self):
         return dsm_mass(self.handle)
 
-    def fields(self):
-        return dsm_fields(self.handle, self.N, self.dim)
+    def fields(self, which=FIELDS):
+        return dsm_fields(self.handle, self.N, self.dim, which)
 
     def diagnostics(self):
         return dsm_diagnostics(self.handle)

@@ -368,13 +368,13 @@ class GpuExecutor:
         from . import workloads as W
 
         w = job.workload
-        f32 = lambda a: W.flat(np.asarray(a, dtype=np.float32).astype(np.float64))  # noqa: E731
         sim = self.dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
                                   gravity=w.gravity, storage=job.storage, device=self.device,
                                   dev_ptr=self.base + offset, rho=w.rho, tau_gas=w.tau_gas or 0.0)
         try:
-            sim.set_solid_field(f32(w.C1))
-            sim.set_liquid(f32(w.C2))
+            # the library rounds the FP64 fields to FP32 itself
+            sim.set_solid_field(W.flat(w.C1))
+            sim.set_liquid(W.flat(w.C2))
             sim.step(1)  # the first step reads at-node populations; later steps run batched
         except Exception:
             sim.close()
@@ -423,7 +423,10 @@ class GpuExecutor:
 
     def finish(self, job) -> dict:
         sim = self.sims.pop(job.id)
-        out = {"C2": sim.fields()["C2"], "mass": sim.mass(), "free_energy": sim.free_energy()[0],
+        # C2 alone (one plane copied), then one FP64 reduction for the masses
+        # and the free energy
+        d = sim.diagnostics()
+        out = {"C2": sim.fields(("C2",))["C2"], "mass": d["mass"], "free_energy": d["free_energy"],
                "steps": sim.steps}
         sim.close()
         return out

@@ -363,6 +363,11 @@ def serve_jobs(count: int, seed: int = 5, steps=(200, 1000), small: bool = False
             if small:
                 n, radius = max(24, n // 4), max(4.0, radius / 4)
             w = particle_at_interface(n, radius, float(rng.uniform(45.0, 135.0)), seed=seed * 7919 + k)
+        # fields held in node order (x fastest), as a client hands them to the
+        # library, so that flat() is a view
+        w.C1, w.C2 = np.asfortranarray(w.C1), np.asfortranarray(w.C2)
+        if w.mask is not None:
+            w.mask = np.asfortranarray(w.mask)
         out.append((w, int(rng.integers(steps[0], steps[1] + 1))))
     return out
 

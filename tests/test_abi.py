@@ -189,3 +189,8 @@ def test_size_limits_are_checked_on_host(lib):
     assert rc == dsm.DSM_EINVAL and "2^32" in dsm.dsm_last_error()
     # a 2D lattice of 2^28 nodes is fine (planes are single rows)
     assert dsm.dsm_required_bytes(dsm.make_params(2, (16384, 16384), (0.01, 0.005, 0.01))) > 0
+
+
+def test_field_selection_is_checked_before_the_library_is_called():
+    with pytest.raises(ValueError):
+        dsm.dsm_fields(None, 16, 2, which=("C2", "rho"))

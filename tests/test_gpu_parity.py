@@ -84,6 +84,12 @@ def test_steps_from_liquid(gpu, dim, kernel):
     Fo, Eo = orc.free_energy()
     assert abs(Fg - Fo) / abs(Fo) < 1e-5
     assert abs(Eg - Eo) <= 1e-3 * abs(Eo) + 1e-12
+    # selected fields: the same values, only those returned
+    for which in (("C2",), ("C3",), ("C1", "u"), ("p",)):
+        sel = sim.fields(which)
+        assert set(sel) == set(which)
+        for k in which:
+            assert np.array_equal(sel[k], fg[k]), k
     # the same FP64 reduction through dsm_diagnostics, with the largest speed
     d = sim.diagnostics()
     assert np.array_equal(d["mass"], m1)
@@ -133,6 +139,8 @@ def test_solid_stage(gpu, dim, storage, bar):
         s.init_solid(700, 1e-3, 2e-4, 1.0, 1.0 / 6.0, 0)
     fg, fo = sim.fields(), orc.fields()
     assert report("C1", fg["C1"], fo["C1"]) < bar
+    assert np.array_equal(sim.fields(("C1",))["C1"], fg["C1"])
+    assert np.array_equal(sim.fields(("C3",))["C3"], fg["C3"])
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
