@@ -497,15 +497,17 @@ int dsm_create(const dsm_params* p, const uint8_t* mask, void* dev_buf, size_t d
         return rc;
     };
     const size_t N = (size_t)s->N;
-    std::vector<uint8_t> m(N, 0);
-    if (mask)
-        for (size_t n = 0; n < N; ++n) m[n] = mask[n] ? 1 : 0;
     // every byte of the buffer starts at zero (padding and unused slots are
-    // never written later, so state images depend only on the inputs)
+    // never written later, so state images depend only on the inputs); with
+    // no mask that is already S empty and C1 = 0
     hipError_t e = hipMemsetAsync(dev_buf, 0, L.total, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->d.mask, m.data(), N, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = launch_c1_from_mask(s->d.mask, s->d.c1, s->N, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->d.flag, 0, 4 * sizeof(int), s->stream);
+    std::vector<uint8_t> m;
+    if (mask) {
+        m.resize(N);
+        for (size_t n = 0; n < N; ++n) m[n] = mask[n] ? 1 : 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(s->d.mask, m.data(), N, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = launch_c1_from_mask(s->d.mask, s->d.c1, s->N, s->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return cleanup(fail(DSM_EDEVICE, std::string("dsm_create: ") + hipGetErrorString(e)));
     // The sharp solid is a solid of the fluid stage like any other: a liquid
