@@ -332,6 +332,7 @@ def run_serve(dsm, W, dev, args, plain_mlups):
     elapsed = S.run_stream(srv, jobs, arrivals)
     rep = S.report(jobs, elapsed)
     peak_gib, rounds = srv.arena.peak / (1 << 30), srv.rounds
+    srv.ex.close()
     del srv
     torch.cuda.empty_cache()
 

@@ -15,6 +15,13 @@ is retired with its error, its arena slot freed, while the others go on:
 the lattices of a batch are independent, so its failure changes no other
 job's result.
 
+Set-up and result readout go through the executor's ``start_async`` and
+``finish_async``: the GPU executor runs them on a worker thread and a stream
+of their own while the resident jobs' quantum runs, so the GPU does not idle
+through them; a job joins the batch at the first quantum boundary after its
+set-up has finished, and its arena slot is freed once its result has been
+read.  The timing-model executor completes both at once.
+
 The scheduling logic (``Arena``, ``Server``, ``run_stream``) is plain host
 code; device work goes through an executor: ``GpuExecutor`` drives the C ABI,
 ``ModelExecutor`` replaces it with a timing model for host-only tests.
@@ -23,6 +30,7 @@ from __future__ import annotations
 
 import collections
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -123,6 +131,8 @@ class Server:
         self.quantum = int(quantum)
         self.queue = collections.deque()
         self.running = []
+        self.setting_up = []  # (job, future of its set-up), in admission order
+        self.finishing = []   # (job, future of (result, time read or None))
         self.done = []
         self.failed = []
         self.changed = False
@@ -131,7 +141,7 @@ class Server:
 
     @property
     def busy(self) -> bool:
-        return bool(self.queue or self.running)
+        return bool(self.queue or self.running or self.setting_up or self.finishing)
 
     def submit(self, job: Job, now: float):
         job.arrival = now
@@ -142,8 +152,7 @@ class Server:
             raise ValueError(f"job {job.id}: steps must be >= 1")
         self.queue.append(job)
 
-    def _admit(self, now: float) -> list:
-        admitted = []
+    def _admit(self, now: float):
         while self.queue:
             job = self.queue[0]
             off = self.arena.alloc(job.nbytes)
@@ -152,16 +161,48 @@ class Server:
             self.queue.popleft()
             job.offset = off
             job.admitted = now
+            self.setting_up.append((job, self.ex.start_async(job, off)))
+
+    def _join(self, now: float, wait: bool) -> bool:
+        """Jobs whose set-up has finished join the resident set (in admission
+        order); with ``wait``, blocks until the oldest set-up has finished.
+        Returns whether any joined."""
+        if wait and self.setting_up:
+            _wait(self.setting_up[0][1])
+        joined, keep = False, []
+        for job, fut in self.setting_up:
+            if not fut.done():
+                keep.append((job, fut))
+                continue
             try:
-                job.done_steps = self.ex.start(job, off)
+                job.done_steps = fut.result()
             except Exception as e:  # noqa: BLE001 (any set-up error fails this job only)
-                self.arena.free(off)
+                self.arena.free(job.offset)
                 job.offset = None
                 self._retire_failed(job, f"{type(e).__name__}: {e}", now)
                 continue
             self.running.append(job)
-            admitted.append(job)
-        return admitted
+            joined = True
+        self.setting_up = keep
+        return joined
+
+    def _collect(self, now: float, wait: bool) -> list:
+        """Jobs whose result has been read: result, finish time, slot freed.
+        With ``wait``, blocks until the oldest readout has finished."""
+        if wait and self.finishing:
+            _wait(self.finishing[0][1])
+        out, keep = [], []
+        for job, fut in self.finishing:
+            if not fut.done():
+                keep.append((job, fut))
+                continue
+            job.result, t_read = fut.result()
+            job.finished = now if t_read is None else t_read
+            self.arena.free(job.offset)
+            self.done.append(job)
+            out.append(job)
+        self.finishing = keep
+        return out
 
     def _retire_failed(self, job: Job, error: str, t: float):
         job.error = error
@@ -197,8 +238,16 @@ class Server:
             self.queue.appendleft(job)
 
     def step(self, now: float, clock=None) -> list:
-        if self._admit(now):
+        """One round; returns the jobs whose results were read in it."""
+        finished = self._collect(now, wait=False)
+        self._admit(now)
+        # with nothing resident, wait for a set-up (else for a readout, which
+        # frees arena room) rather than spin
+        idle = not self.running
+        if self._join(now, wait=idle):
             self.changed = True
+        if not self.running and not self.setting_up:
+            finished += self._collect(clock() if clock else now, wait=idle)
         if self.changed:
             self._rebuild()
             self.changed = False
@@ -218,15 +267,38 @@ class Server:
             self.running.remove(j)
             self._retire_failed(j, failed[j.id], t)
             self.changed = True
-        finished = [j for j in self.running if j.done_steps >= j.steps]
-        for j in finished:
-            j.result = self.ex.finish(j)
-            self.arena.free(j.offset)
-            j.finished = t
+        for j in [j for j in self.running if j.done_steps >= j.steps]:
             self.running.remove(j)
-            self.done.append(j)
+            self.finishing.append((j, self.ex.finish_async(j, clock)))
             self.changed = True
-        return finished
+        return finished + self._collect(t, wait=False)
+
+
+def _wait(fut):
+    """Blocks until a future has finished (its outcome is read later)."""
+    if not fut.done():
+        try:
+            fut.result()
+        except Exception:  # noqa: BLE001 (handled where the result is read)
+            pass
+
+
+class _Done:
+    """A future that has already finished (for executors without a worker)."""
+
+    def __init__(self, fn, *args):
+        try:
+            self._value, self._error = fn(*args), None
+        except Exception as e:  # noqa: BLE001 (re-raised by result())
+            self._value, self._error = None, e
+
+    def done(self) -> bool:
+        return True
+
+    def result(self):
+        if self._error is not None:
+            raise self._error
+        return self._value
 
 
 def run_stream(server: Server, jobs, arrivals, clock=time.perf_counter, sleep=time.sleep):
@@ -285,6 +357,7 @@ class ModelExecutor:
         self.rate, self.overhead, self.bpn = rate, overhead, bytes_per_node
         self.t = 0.0
         self.resident = {}
+        self.members = set()  # job ids of the last rebuild: the ones a quantum steps
         self.log = []
         self.fail_start = set(fail_start)   # job ids whose set-up is rejected
         self.fail_at = dict(fail_at or {})  # job id -> step at which it goes non-finite
@@ -297,6 +370,12 @@ class ModelExecutor:
 
     def job_bytes(self, job) -> int:
         return job.nodes * self.bpn + 4096
+
+    def start_async(self, job, offset):
+        return _Done(self.start, job, offset)
+
+    def finish_async(self, job, clock=None):
+        return _Done(lambda: (self.finish(job), None))
 
     def start(self, job, offset) -> int:
         if job.id in self.fail_start:
@@ -312,16 +391,18 @@ class ModelExecutor:
         return out
 
     def rebuild(self, running, blocks):
-        self.log.append(("rebuild", sorted(j.id for j in running)))
+        self.members = {j.id for j in running}
+        self.log.append(("rebuild", sorted(self.members)))
 
     def advance(self, n: int) -> dict:
         failed = {}
-        for jid, r in self.resident.items():
+        stepped = {jid: r for jid, r in self.resident.items() if jid in self.members}
+        for jid, r in stepped.items():
             r["steps"] += n
             if jid in self.fail_at and r["steps"] >= self.fail_at[jid]:
                 failed[jid] = "non-finite values"
-        nodes = sum(r["nodes"] for r in self.resident.values())
-        self.log.append(("advance", n, sorted(self.resident)))
+        nodes = sum(r["nodes"] for r in stepped.values())
+        self.log.append(("advance", n, sorted(stepped)))
         self.t += self.overhead + n * nodes / self.rate
         return failed
 
@@ -335,7 +416,14 @@ class ModelExecutor:
 
 class GpuExecutor:
     """Device side of the server: one torch buffer as the arena, one
-    Simulation per resident job carved from it, one Batch per storage."""
+    Simulation per resident job carved from it, one Batch per storage.
+
+    Set-up and readout run on one worker thread, with the jobs' handles on
+    a stream of their own; the batches step on another stream from the
+    request loop's thread.  A set-up ends by synchronising its stream (the
+    job's state is complete before any batch reads it), a readout starts
+    after the quantum that finished the job has been synchronised, and a
+    job's handle is used by one thread at a time."""
 
     def __init__(self, capacity: int, device="cuda:0"):
         import torch
@@ -344,14 +432,33 @@ class GpuExecutor:
 
         self.dsm = dsm
         dsm.load()  # raises if the HIP library is missing: there is no fallback
+        self.torch = torch
         self.device = torch.device(device)
         self.buffer = torch.empty(capacity + 2 * ALIGN, dtype=torch.uint8, device=self.device)
         self.base = (self.buffer.data_ptr() + ALIGN - 1) // ALIGN * ALIGN
         self.capacity = capacity
+        # default-priority streams, neither of them the null stream, so that
+        # set-up and readout overlap the batched steps
+        self.job_stream = torch.cuda.Stream(self.device)
+        self.batch_stream = torch.cuda.Stream(self.device)
+        torch.cuda.synchronize(self.device)  # the arena's allocation is complete
+        self.worker = ThreadPoolExecutor(max_workers=1)
         self.sims = {}
         self.batches = {}
         self.members = {}  # batch key -> job ids, in member order
         self.table_base = None
+
+    def start_async(self, job, offset):
+        return self.worker.submit(self.start, job, offset)
+
+    def finish_async(self, job, clock=None):
+        def read():
+            out = self.finish(job)
+            return out, (clock() if clock else None)
+        return self.worker.submit(read)
+
+    def close(self):
+        self.worker.shutdown(wait=True)
 
     def set_table_base(self, base: int):
         self.table_base = base
@@ -368,14 +475,17 @@ class GpuExecutor:
         from . import workloads as W
 
         w = job.workload
+        self.torch.cuda.set_device(self.device)  # this thread's current device
         sim = self.dsm.Simulation(w.dim, w.shape, w.kappa, alpha=w.alpha, tau=w.tau, mobility=w.mobility,
                                   gravity=w.gravity, storage=job.storage, device=self.device,
-                                  dev_ptr=self.base + offset, rho=w.rho, tau_gas=w.tau_gas or 0.0)
+                                  stream=self.job_stream, dev_ptr=self.base + offset, rho=w.rho,
+                                  tau_gas=w.tau_gas or 0.0)
         try:
             # the library rounds the FP64 fields to FP32 itself
             sim.set_solid_field(W.flat(w.C1))
             sim.set_liquid(W.flat(w.C2))
             sim.step(1)  # the first step reads at-node populations; later steps run batched
+            self.job_stream.synchronize()
         except Exception:
             sim.close()
             raise
@@ -396,7 +506,7 @@ class GpuExecutor:
         for j in running:
             self.members.setdefault(j.storage, []).append(j.id)
         for key, ids in self.members.items():
-            b = self.dsm.Batch([self.sims[i] for i in ids], device=self.device,
+            b = self.dsm.Batch([self.sims[i] for i in ids], device=self.device, stream=self.batch_stream,
                                dev_ptr=self.table_base + blocks[key])
             b.tune()
             self.batches[key] = b
@@ -422,6 +532,7 @@ class GpuExecutor:
         return failed
 
     def finish(self, job) -> dict:
+        self.torch.cuda.set_device(self.device)  # this thread's current device
         sim = self.sims.pop(job.id)
         # C2 alone (one plane copied), then one FP64 reduction for the masses
         # and the free energy

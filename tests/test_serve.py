@@ -2,7 +2,10 @@
 the request loop driven by a timing-model executor (admission by footprint,
 first in first out, joining at quantum boundaries, exact step counts,
 retirement, latency report)."""
+import threading
+import time
 import types
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -170,3 +173,62 @@ def test_failed_jobs_are_retired_and_the_others_finish():
     assert srv.arena.used == 0 and not srv.busy and not ex.resident
     rep = S.report(jobs, elapsed)
     assert rep["jobs"] == 8 and rep["failed_jobs"] == 2
+
+
+def test_set_up_and_readout_on_a_worker_thread():
+    """Set-ups and readouts that finish later than they were started (on a
+    worker thread, as the GPU executor runs them): every job still runs
+    exactly its steps, a job is stepped only after its set-up has finished,
+    its arena slot is freed only after its result has been read, and a
+    rejected set-up is retired."""
+
+    class Worker(S.ModelExecutor):
+        def __init__(self):
+            super().__init__(rate=1e9, overhead=1e-4, fail_start={4})
+            self.pool = ThreadPoolExecutor(max_workers=1)
+            self.lock = threading.Lock()
+            self.set_up, self.read = set(), set()
+
+        def start_async(self, job, offset):
+            def run():
+                time.sleep(0.001)
+                with self.lock:
+                    r = self.start(job, offset)
+                    self.set_up.add(job.id)
+                    return r
+            return self.pool.submit(run)
+
+        def finish_async(self, job, clock=None):
+            def run():
+                time.sleep(0.001)
+                with self.lock:
+                    out = self.finish(job)
+                    self.read.add(job.id)
+                    return out, None
+            return self.pool.submit(run)
+
+        def advance(self, n):
+            with self.lock:
+                assert self.members <= self.set_up  # never a job still being set up
+                return super().advance(n)
+
+    ex = Worker()
+    srv = S.Server(ex, 100 << 20, quantum=10)
+    jobs = [job(k, (40, 40, 40), 30 + 7 * k) for k in range(8)]
+    freed = []
+    orig_free = srv.arena.free
+
+    def free(off):
+        owner = [j for j in jobs if j.offset == off and j.result is not None]
+        freed.append((off, [j.id for j in owner if j.id not in ex.read]))
+        orig_free(off)
+
+    srv.arena.free = free
+    S.run_stream(srv, jobs, [0.0003 * k for k in range(8)], clock=ex.now, sleep=ex.sleep)
+    ex.pool.shutdown()
+    assert "rejected" in jobs[4].error and jobs[4].result is None
+    for j in jobs:
+        if j.id != 4:
+            assert j.error is None and j.result["steps"] == j.steps
+    assert all(not early for _, early in freed)  # no slot freed before its readout
+    assert srv.arena.used == 0 and not srv.busy and not ex.resident
