@@ -100,26 +100,28 @@ def test_steps_from_liquid(gpu, dim, kernel):
     assert d["nonfinite_nodes"] == 0.0
 
 
+@pytest.mark.parametrize("storage,bar", [(dsm.DSM_STORAGE_FP32, 1e-5), (dsm.DSM_STORAGE_FP16, 2e-3)])
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("dim", [2, 3])
-def test_liquid_on_the_sharp_mask(gpu, dim, kernel):
+def test_liquid_on_the_sharp_mask(gpu, dim, kernel, storage, bar):
     """A liquid set right after creation on the sharp solid C1 = 1[S], with no
     solid stage: the cut links of the sharp field, built at creation, against
-    the oracle's bounce-back on the same field, 300 steps."""
+    the oracle's bounce-back on the same field, 300 steps (FP16 population
+    storage to its bar)."""
     shape = SHAPES[dim]
     mask, _, _ = wall_and_particle(dim, shape, seed=41)
     C1 = mask.astype(np.float64)
     centre = [0.6 * n for n in shape[:-1]] + [3.5]
     C2 = f32(W.flat(W.drop_field(shape, centre, 0.3 * min(shape), C1, open_axis=dim - 1)))
     grav = (2e-5, 0.0, 0.0) if dim == 2 else (2e-5, 1e-5, 0.0)
-    sim, orc = pair(dim, shape, kernel, gravity=grav, mask=W.flat(mask))
+    sim, orc = pair(dim, shape, kernel, gravity=grav, mask=W.flat(mask), storage=storage)
     for s in (sim, orc):
         s.set_liquid(C2)
         s.step(300)
     fg, fo = sim.fields(), orc.fields()
     assert np.array_equal(fg["C1"], W.flat(C1))
-    assert report("C2", fg["C2"], fo["C2"]) < 1e-5
-    assert report("u", fg["u"], fo["u"]) < 1e-6
+    assert report("C2", fg["C2"], fo["C2"]) < bar
+    assert report("u", fg["u"], fo["u"]) < bar / 10
     assert np.abs(fo["u"]).max() > 1e-6  # the flow is not trivial
 
 
