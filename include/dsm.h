@@ -270,10 +270,11 @@ long long dsm_step_count(const dsm_sim* s);
  * kernel's tiles per compute unit) times planes; 2D variant 0 with 16 planes, or 8 when the
  * lattice has too few 256-column tiles to give every compute unit whole
  * rounds of 16-plane marches.  dsm_create replaces that default by another
- * variant and a march of 8, 16 or 32 planes when a model of the step's
- * duration (work over resident waves, per-variant wave cost, fill planes and
- * tail) predicts it at least 10 % faster, as for narrow 2D rows, small cubes
- * and rows just wider than a tile.
+ * variant and a march of 8, 16 or 32 planes (in 2D also 4, for a variant
+ * whose 8-plane grid makes less than one round of resident workgroups) when
+ * a model of the step's duration (work over resident waves, per-variant wave
+ * cost, fill planes and tail) predicts it at least 10 % faster, as for
+ * narrow 2D rows, small lattices and rows just wider than a tile.
  * Errors: DSM_EINVAL. */
 int dsm_set_tiling(dsm_sim* s, int variant, int planes);
 /* The launch shape in use (the default chosen by dsm_create, or the last

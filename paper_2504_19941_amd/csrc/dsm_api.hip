@@ -403,16 +403,30 @@ int default_planes(const Geom& g, int dim, int slots) {
 // widths 100-1000, cubes 64-160) that never chose a slower tiling and gained
 // 10 % on average, e.g. D2Q9 300 x 8192 at 29.6 GLUPS against 26.0 and
 // D3Q19 64^3 at 6.8 against 3.5.  Every tiling gives bit-identical results.
+// A 2D lattice whose 8-row marches of a variant make less than one round of
+// resident workgroups is bound by the latency of its marches, and that
+// variant also gets 4-row marches: D2Q9 128 x 64, 256^2 and 512 x 128 step in
+// 11.9-13.2 us against 18.2-19.7, D2Q9 100 x 4096 in 21.0 against 22.6 (FP16
+// 18.1 against 23.3); grids of a round or more keep 8 rows or longer (300 x
+// 8192: 85.0 us with 8, 87.7 with 4).
 static void default_tiling_by_model(dsm_sim* s, int cus) {
     const int dim = s->p.dim, rho = make_phys(s, 2).contrast;
     auto cost = [&](int v, int planes) {
         return lattice_schedule_cost(s->geom, dim, v, planes, fused_blocks_per_cu(dim, v, s->half, rho), cus);
     };
+    auto under_one_round = [&](int v, int planes) {
+        int tx = 0, ty = 0;
+        fused_tile_shape(dim, v, &tx, &ty);
+        const long long items = (long long)((s->geom.X + tx - 1) / tx) * ((s->geom.Y + ty - 1) / ty) *
+                                ((s->geom.Z + planes - 1) / planes);
+        return items < (long long)cus * fused_blocks_per_cu(dim, v, s->half, rho);
+    };
     const double c0 = cost(s->tile_variant, s->tile_planes);
     double best = c0;
     int bv = s->tile_variant, bp = s->tile_planes;
     for (int v = 0; v < fused_tile_variants(dim); ++v)
-        for (int planes : {8, 16, 32}) {
+        for (int planes : {4, 8, 16, 32}) {
+            if (planes == 4 && !(dim == 2 && under_one_round(v, 8))) continue;
             const double c = cost(v, planes);
             if (c < best) best = c, bv = v, bp = planes;
         }

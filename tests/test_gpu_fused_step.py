@@ -95,7 +95,9 @@ def test_default_tiling_and_its_readback(gpu):
     96 planes (FP32) and 48 (FP16) for the 256 x 256 x 192 pillar lattice,
     one round of tiles each; 8 planes for an 80^3 FP32 lattice, too small
     to fill the chip with 16;
-    64-column tiles with 8-row marches for a D2Q9 lattice 300 columns wide."""
+    64-column tiles with 8-row marches for a D2Q9 lattice 300 columns wide;
+    4-row marches for D2Q9 lattices whose 8-row grid makes less than one
+    round (128 x 64 on 256-column tiles, 100 x 4096 on 128-column tiles)."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     cases = [(3, (128, 128, 128), dsm.DSM_STORAGE_FP32, (2, 16)),
@@ -103,11 +105,13 @@ def test_default_tiling_and_its_readback(gpu):
              (3, (256, 256, 192), dsm.DSM_STORAGE_FP32, (2, 96)),
              (3, (256, 256, 192), dsm.DSM_STORAGE_FP16, (2, 48)),
              (3, (80, 80, 80), dsm.DSM_STORAGE_FP32, (2, 8)),
-             (2, (300, 8192), dsm.DSM_STORAGE_FP32, (2, 8))]
+             (2, (300, 8192), dsm.DSM_STORAGE_FP32, (2, 8)),
+             (2, (128, 64), dsm.DSM_STORAGE_FP32, (0, 4)),
+             (2, (100, 4096), dsm.DSM_STORAGE_FP16, (1, 4))]
     for dim, shape, storage, expect in cases:
         sim = dsm.Simulation(dim, shape, KAPPA, storage=storage)
         variant, planes = sim.tiling()
-        assert 0 <= variant < dsm.dsm_tiling_variants(dim) and planes in (8, 16, 32, 48, 64, 96, 128)
+        assert 0 <= variant < dsm.dsm_tiling_variants(dim) and planes in (4, 8, 16, 32, 48, 64, 96, 128)
         if cus == 256:
             assert (variant, planes) == expect, (shape, storage, (variant, planes))
         sim.set_tiling(0, 12)
