@@ -361,6 +361,23 @@ double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
 
 }  // namespace
 
+// Latency-bound form for one lattice whose grid makes a fraction of a round:
+// every item marches at once, so the step lasts whole rounds of the longest
+// march, each fill plane counting 0.75 of a plane (fitted to 22 small 3D
+// lattices, 48^3 to 128^3 and two oblong ones, FP32 and FP16, timed over
+// every tile variant and marches of 2 to 32 planes).  Tiles wider than the
+// lattice row, rounded to whole waves, are charged their idle waves.
+double dsm::lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus) {
+    int tx = 0, ty = 0;
+    fused_tile_shape(dim, variant, &tx, &ty);
+    const long long tiles_x = (g.X + tx - 1) / tx;
+    const long long items = tiles_x * ((g.Y + ty - 1) / ty) * ((g.Z + planes - 1) / planes);
+    const long long slots = std::max(1LL, (long long)cus * blocks_per_cu);
+    const long long rounds = (items + slots - 1) / slots;
+    const double idle = (double)(tiles_x * tx) / (double)((g.X + 63) / 64 * 64);
+    return kWaveCost[dim - 2][variant] * idle * (double)rounds * (std::min(planes, g.Z) + 2.0 * 0.75);
+}
+
 double dsm::lattice_schedule_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus) {
     int tx = 0, ty = 0;
     fused_tile_shape(dim, variant, &tx, &ty);
