@@ -274,10 +274,11 @@ long long dsm_step_count(const dsm_sim* s);
  * whose 8-plane grid makes less than one round of resident workgroups) when
  * a model of the step's duration (work over resident waves, per-variant wave
  * cost, fill planes and tail) predicts it at least 10 % faster, as for
- * narrow 2D rows, small lattices and rows just wider than a tile.  A 3D
+ * narrow 2D rows, small lattices and rows just wider than a tile.  A
  * lattice whose default grid fills at most half a round of resident
  * workgroups is instead scored by whole rounds of its longest march, over
- * marches of 2 to 32 planes (small lattices, whose marches all run at once).
+ * marches of 2 to 32 planes in 3D and 1 to 32 rows in 2D (small lattices,
+ * whose marches all run at once).
  * Errors: DSM_EINVAL. */
 int dsm_set_tiling(dsm_sim* s, int variant, int planes);
 /* The launch shape in use (the default chosen by dsm_create, or the last
@@ -287,7 +288,7 @@ int dsm_get_tiling(const dsm_sim* s, int* variant, int* planes);
 int dsm_tiling_variants(int dim);
 
 /* Measured tiling tuner: times every tile variant with each march of 2, 4,
- * 8, 16, 32, 48, 64, 96 and 128 planes (3D) or 2, 4, 8, 16, 32, 64 and 128 (2D),
+ * 8, 16, 32, 48, 64, 96 and 128 planes (3D) or 1, 2, 4, 8, 16, 32, 64 and 128 (2D),
  * marches of Z planes or more timed once, on the lattice itself (one
  * untimed step, then reps steps timed as dsm_step_timed times them) and
  * installs the fastest.  Results do not depend on the tiling; the lattice

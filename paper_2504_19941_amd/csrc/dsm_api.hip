@@ -410,16 +410,18 @@ int default_planes(const Geom& g, int dim, int slots) {
 // 18.1 against 23.3); grids of a round or more keep 8 rows or longer (300 x
 // 8192: 85.0 us with 8, 87.7 with 4).
 //
-// A 3D lattice whose default grid fills at most half a round is latency-bound
+// A lattice whose default grid fills at most half a round is latency-bound
 // as a whole: its marches all run at once, so the step lasts the longest
-// march (whole rounds of it), and 2- or 4-plane marches beat the default's
-// despite their fill planes.  For those the latency form of the model
+// march (whole rounds of it), and short marches beat the default's despite
+// their fill planes.  For those the latency form of the model
 // (lattice_latency_cost) picks among every variant and marches of 2-32
-// planes, again only when it predicts 10 % or more.  Measured (fused kernel):
-// 48^3 22.7 us against 37.9 with the 8-plane default (FP16 20.1 against
-// 38.1), 64^3 23.8 against 38.4 (FP16 21.1 against 39.1), 128 x 64 x 64
-// 39.7 against 53.4 (FP16 29.7 against 47.2), 80^3 FP16 46.0 against 48.0;
-// over 26 lattices from 48^3 to 160^3 none was slower.
+// planes (1-32 rows in 2D), again only when it predicts 10 % or more.
+// Measured (fused kernel): 48^3 22.7 us against 37.9 with the 8-plane
+// default (FP16 20.1 against 38.1), 64^3 23.8 against 38.4 (FP16 21.1
+// against 39.1), 128 x 64 x 64 39.7 against 53.4 (FP16 29.7 against 47.2),
+// 80^3 FP16 46.0 against 48.0; D2Q9 128 x 64 7.4 against 12.4 with 4-row
+// marches, 256^2 8.4 against 12.9, 64 x 2048 9.8 against 12.4, 512^2 FP16
+// 13.1 against 14.6.  Over 26 3D and 22 2D lattices none was slower.
 static void default_tiling_by_model(dsm_sim* s, int cus) {
     const int dim = s->p.dim, rho = make_phys(s, 2).contrast;
     auto bpc = [&](int v) { return fused_blocks_per_cu(dim, v, s->half, rho); };
@@ -429,13 +431,14 @@ static void default_tiling_by_model(dsm_sim* s, int cus) {
         return (long long)((s->geom.X + tx - 1) / tx) * ((s->geom.Y + ty - 1) / ty) *
                ((s->geom.Z + planes - 1) / planes);
     };
-    if (dim == 3 && 2 * items_of(s->tile_variant, s->tile_planes) <= (long long)cus * bpc(s->tile_variant)) {
+    if (2 * items_of(s->tile_variant, s->tile_planes) <= (long long)cus * bpc(s->tile_variant)) {
         auto lcost = [&](int v, int planes) { return lattice_latency_cost(s->geom, dim, v, planes, bpc(v), cus); };
         const double l0 = lcost(s->tile_variant, s->tile_planes);
         double best = l0;
         int bv = s->tile_variant, bp = s->tile_planes;
         for (int v = 0; v < fused_tile_variants(dim); ++v)
-            for (int planes : {2, 4, 8, 16, 32}) {
+            for (int planes : {1, 2, 4, 8, 16, 32}) {
+                if (planes == 1 && dim == 3) continue;  // 3D marches were measured from 2 planes
                 const double c = lcost(v, planes);
                 if (c < best) best = c, bv = v, bp = planes;
             }
@@ -957,7 +960,7 @@ int dsm_tune_tiling(dsm_sim* s, int reps, double* ms_per_step) {
     if (s->stage != 2) return fail(DSM_ESTATE, "dsm_tune_tiling needs a liquid (dsm_set_liquid) first");
     if (s->p.kernel != DSM_KERNEL_FUSED) return fail(DSM_EINVAL, "dsm_tune_tiling tunes the fused kernel only");
     static const int kPlanes3[] = {2, 4, 8, 16, 32, 48, 64, 96, 128};
-    static const int kPlanes2[] = {2, 4, 8, 16, 32, 64, 128};
+    static const int kPlanes2[] = {1, 2, 4, 8, 16, 32, 64, 128};
     const int dim = s->p.dim, Z = s->geom.Z;
     const int* list = dim == 3 ? kPlanes3 : kPlanes2;
     const int count = dim == 3 ? (int)(sizeof(kPlanes3) / sizeof(int)) : (int)(sizeof(kPlanes2) / sizeof(int));

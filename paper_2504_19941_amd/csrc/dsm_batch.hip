@@ -363,19 +363,24 @@ double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
 
 // Latency-bound form for one lattice whose grid makes a fraction of a round:
 // every item marches at once, so the step lasts whole rounds of the longest
-// march, each fill plane counting 0.75 of a plane (fitted to 22 small 3D
-// lattices, 48^3 to 128^3 and two oblong ones, FP32 and FP16, timed over
-// every tile variant and marches of 2 to 32 planes).  Tiles wider than the
-// lattice row, rounded to whole waves, are charged their idle waves.
+// march plus its fill planes.  Rounds are counted against a share of the
+// resident workgroups (a full round of 2D items already contends), and tiles
+// wider than the lattice row, rounded to whole waves, are charged their idle
+// waves.  Constants fitted to small lattices timed over every tile variant
+// and march: 22 in 3D (48^3 to 128^3 and two oblong ones, marches of 2 to 32
+// planes) and 22 in 2D (128 x 64 to 2048^2, marches of 1 to 32 rows), FP32
+// and FP16 each.
+constexpr double kLatencyFill[2] = {0.5, 0.75};   // fill plane, as a share of a plane
+constexpr double kLatencySlots[2] = {0.5, 1.0};   // share of the resident workgroups per round
 double dsm::lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus) {
     int tx = 0, ty = 0;
     fused_tile_shape(dim, variant, &tx, &ty);
     const long long tiles_x = (g.X + tx - 1) / tx;
     const long long items = tiles_x * ((g.Y + ty - 1) / ty) * ((g.Z + planes - 1) / planes);
-    const long long slots = std::max(1LL, (long long)cus * blocks_per_cu);
-    const long long rounds = (items + slots - 1) / slots;
+    const double slots = std::max(1.0, kLatencySlots[dim - 2] * (double)cus * blocks_per_cu);
+    const double rounds = std::ceil((double)items / slots);
     const double idle = (double)(tiles_x * tx) / (double)((g.X + 63) / 64 * 64);
-    return kWaveCost[dim - 2][variant] * idle * (double)rounds * (std::min(planes, g.Z) + 2.0 * 0.75);
+    return kWaveCost[dim - 2][variant] * idle * rounds * (std::min(planes, g.Z) + 2.0 * kLatencyFill[dim - 2]);
 }
 
 double dsm::lattice_schedule_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus) {

@@ -96,10 +96,9 @@ def test_default_tiling_and_its_readback(gpu):
     one round of tiles each; 8 planes for an 80^3 FP32 lattice, too small
     to fill the chip with 16;
     64-column tiles with 8-row marches for a D2Q9 lattice 300 columns wide;
-    4-row marches for D2Q9 lattices whose 8-row grid makes less than one
-    round (128 x 64 on 256-column tiles, 100 x 4096 on 128-column tiles);
-    2-plane marches on 64-column tiles for a 64^3 lattice, whose default
-    grid fills under half a round."""
+    1-row marches on 128-column tiles for D2Q9 128 x 64 and 4-row marches
+    on 128-column tiles for 100 x 4096, whose default grids fill at most half
+    a round; 2-plane marches on 64-column tiles for a 64^3 lattice, likewise."""
     import torch
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     cases = [(3, (128, 128, 128), dsm.DSM_STORAGE_FP32, (2, 16)),
@@ -108,14 +107,14 @@ def test_default_tiling_and_its_readback(gpu):
              (3, (256, 256, 192), dsm.DSM_STORAGE_FP16, (2, 48)),
              (3, (80, 80, 80), dsm.DSM_STORAGE_FP32, (2, 8)),
              (2, (300, 8192), dsm.DSM_STORAGE_FP32, (2, 8)),
-             (2, (128, 64), dsm.DSM_STORAGE_FP32, (0, 4)),
+             (2, (128, 64), dsm.DSM_STORAGE_FP32, (1, 1)),
              (2, (100, 4096), dsm.DSM_STORAGE_FP16, (1, 4)),
              (3, (64, 64, 64), dsm.DSM_STORAGE_FP32, (0, 2)),
              (3, (64, 64, 64), dsm.DSM_STORAGE_FP16, (0, 2))]
     for dim, shape, storage, expect in cases:
         sim = dsm.Simulation(dim, shape, KAPPA, storage=storage)
         variant, planes = sim.tiling()
-        assert 0 <= variant < dsm.dsm_tiling_variants(dim) and planes in (2, 4, 8, 16, 32, 48, 64, 96, 128)
+        assert 0 <= variant < dsm.dsm_tiling_variants(dim) and planes in (1, 2, 4, 8, 16, 32, 48, 64, 96, 128)
         if cus == 256:
             assert (variant, planes) == expect, (shape, storage, (variant, planes))
         sim.set_tiling(0, 12)
