@@ -36,5 +36,9 @@ namespace dsm {
 int set_error(int code, const std::string& msg);
 // Step parameters of stage 1 (solid) or 2 (fluid) of a lattice.
 Phys sim_phys(const dsm_sim* s, int stage);
+// Modelled duration of one step of a lattice whose grid makes a fraction of
+// a round, where the step lasts whole rounds of its longest march
+// (dsm_batch.hip; the throughput form is lattice_schedule_cost).
+double lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus);
 
 }  // namespace dsm

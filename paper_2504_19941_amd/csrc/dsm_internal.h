@@ -123,9 +123,6 @@ int fused_blocks_per_cu(int dim, int variant, int half, int rho);
 // the schedule model of the batched step with this lattice as its only member
 // and blocks_per_cu workgroups resident per CU.
 double lattice_schedule_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus);
-// The same for a lattice whose grid makes a fraction of a round, where the
-// step lasts whole rounds of its longest march (dsm_batch.hip).
-double lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus);
 hipError_t launch_bounce_batch(const BatchInst* inst, const BatchChunk* chunks, int nchunks, int parity,
                                int* counters, int ncounters, hipStream_t st);
 hipError_t launch_batch_flags(const BatchInst* inst, int count, int* out, hipStream_t st);
