@@ -421,7 +421,10 @@ int default_planes(const Geom& g, int dim, int slots) {
 // against 39.1), 128 x 64 x 64 39.7 against 53.4 (FP16 29.7 against 47.2),
 // 80^3 FP16 46.0 against 48.0; D2Q9 128 x 64 7.4 against 12.4 with 4-row
 // marches, 256^2 8.4 against 12.9, 64 x 2048 9.8 against 12.4, 512^2 FP16
-// 13.1 against 14.6.  Over 26 3D and 22 2D lattices none was slower.
+// 13.1 against 14.6.  Over 26 3D and 22 2D lattices none was slower.  In 3D
+// with FP16 elements, whose rounds overlap (two tiles per CU), the form also
+// covers grids of up to 0.75 of a round: 96^3 66.6 against 77.8 us, 104^3
+// 68.7 against 80.0, 96 x 96 x 192 116.0 against 142.1.
 static void default_tiling_by_model(dsm_sim* s, int cus) {
     const int dim = s->p.dim, rho = make_phys(s, 2).contrast;
     auto bpc = [&](int v) { return fused_blocks_per_cu(dim, v, s->half, rho); };
@@ -431,8 +434,11 @@ static void default_tiling_by_model(dsm_sim* s, int cus) {
         return (long long)((s->geom.X + tx - 1) / tx) * ((s->geom.Y + ty - 1) / ty) *
                ((s->geom.Z + planes - 1) / planes);
     };
-    if (2 * items_of(s->tile_variant, s->tile_planes) <= (long long)cus * bpc(s->tile_variant)) {
-        auto lcost = [&](int v, int planes) { return lattice_latency_cost(s->geom, dim, v, planes, bpc(v), cus); };
+    const double bound = dim == 3 && s->half ? 0.75 : 0.5;  // share of a round
+    if ((double)items_of(s->tile_variant, s->tile_planes) <= bound * cus * bpc(s->tile_variant)) {
+        auto lcost = [&](int v, int planes) {
+            return lattice_latency_cost(s->geom, dim, v, planes, bpc(v), cus, s->half);
+        };
         const double l0 = lcost(s->tile_variant, s->tile_planes);
         double best = l0;
         int bv = s->tile_variant, bp = s->tile_planes;

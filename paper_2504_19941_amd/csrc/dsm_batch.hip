@@ -369,15 +369,19 @@ double schedule_cost(const dsm_batch* b, int dim, int variant, int planes) {
 // waves.  Constants fitted to small lattices timed over every tile variant
 // and march: 22 in 3D (48^3 to 128^3 and two oblong ones, marches of 2 to 32
 // planes) and 22 in 2D (128 x 64 to 2048^2, marches of 1 to 32 rows), FP32
-// and FP16 each.
+// and FP16 each.  With FP16 elements two 3D tiles share a CU and the marches
+// of consecutive rounds overlap, so a round holds 1.5 times the resident
+// workgroups.
 constexpr double kLatencyFill[2] = {0.5, 0.75};   // fill plane, as a share of a plane
-constexpr double kLatencySlots[2] = {0.5, 1.0};   // share of the resident workgroups per round
-double dsm::lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus) {
+constexpr double kLatencySlots[2][2] = {{0.5, 0.5}, {1.0, 1.5}};  // [2D, 3D][FP32, FP16]: workgroups per round
+double dsm::lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus,
+                                 int half) {
     int tx = 0, ty = 0;
     fused_tile_shape(dim, variant, &tx, &ty);
     const long long tiles_x = (g.X + tx - 1) / tx;
     const long long items = tiles_x * ((g.Y + ty - 1) / ty) * ((g.Z + planes - 1) / planes);
-    const double slots = std::max(1.0, kLatencySlots[dim - 2] * (double)cus * blocks_per_cu);
+    const double share = kLatencySlots[dim - 2][half ? 1 : 0];
+    const double slots = std::max(1.0, share * (double)cus * blocks_per_cu);
     const double rounds = std::ceil((double)items / slots);
     const double idle = (double)(tiles_x * tx) / (double)((g.X + 63) / 64 * 64);
     return kWaveCost[dim - 2][variant] * idle * rounds * (std::min(planes, g.Z) + 2.0 * kLatencyFill[dim - 2]);

@@ -39,6 +39,6 @@ Phys sim_phys(const dsm_sim* s, int stage);
 // Modelled duration of one step of a lattice whose grid makes a fraction of
 // a round, where the step lasts whole rounds of its longest march
 // (dsm_batch.hip; the throughput form is lattice_schedule_cost).
-double lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus);
+double lattice_latency_cost(const Geom& g, int dim, int variant, int planes, int blocks_per_cu, int cus, int half);
 
 }  // namespace dsm
