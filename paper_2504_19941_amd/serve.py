@@ -196,9 +196,13 @@ class Server:
             if not fut.done():
                 keep.append((job, fut))
                 continue
-            job.result, t_read = fut.result()
-            job.finished = now if t_read is None else t_read
             self.arena.free(job.offset)
+            try:
+                job.result, t_read = fut.result()
+            except Exception as e:  # noqa: BLE001 (a failed readout fails this job only)
+                self._retire_failed(job, f"{type(e).__name__}: {e}", now)
+                continue
+            job.finished = now if t_read is None else t_read
             self.done.append(job)
             out.append(job)
         self.finishing = keep

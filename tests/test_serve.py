@@ -180,7 +180,7 @@ def test_set_up_and_readout_on_a_worker_thread():
     worker thread, as the GPU executor runs them): every job still runs
     exactly its steps, a job is stepped only after its set-up has finished,
     its arena slot is freed only after its result has been read, and a
-    rejected set-up is retired."""
+    rejected set-up and a failed readout each retire their job alone."""
 
     class Worker(S.ModelExecutor):
         def __init__(self):
@@ -204,6 +204,8 @@ def test_set_up_and_readout_on_a_worker_thread():
                 with self.lock:
                     out = self.finish(job)
                     self.read.add(job.id)
+                    if job.id == 6:
+                        raise RuntimeError("readout of job 6 failed")
                     return out, None
             return self.pool.submit(run)
 
@@ -219,16 +221,18 @@ def test_set_up_and_readout_on_a_worker_thread():
     orig_free = srv.arena.free
 
     def free(off):
-        owner = [j for j in jobs if j.offset == off and j.result is not None]
-        freed.append((off, [j.id for j in owner if j.id not in ex.read]))
+        # every job that held this slot and got past its set-up has been read
+        owners = [j.id for j in jobs if j.offset == off and j.id in ex.set_up]
+        freed.append((off, [i for i in owners if i not in ex.read]))
         orig_free(off)
 
     srv.arena.free = free
     S.run_stream(srv, jobs, [0.0003 * k for k in range(8)], clock=ex.now, sleep=ex.sleep)
     ex.pool.shutdown()
     assert "rejected" in jobs[4].error and jobs[4].result is None
+    assert "readout of job 6 failed" in jobs[6].error and jobs[6].result is None
     for j in jobs:
-        if j.id != 4:
+        if j.id not in (4, 6):
             assert j.error is None and j.result["steps"] == j.steps
     assert all(not early for _, early in freed)  # no slot freed before its readout
     assert srv.arena.used == 0 and not srv.busy and not ex.resident
