@@ -250,8 +250,10 @@ FIELDS = ("C1", "C2", "C3", "u", "p")
 
 
 def dsm_fields(h, N, dim, which=FIELDS):
-    """The requested fields (names from FIELDS) as FP64 host arrays; the
-    library computes and copies only those."""
+    """The requested fields (names from FIELDS, or one name) as FP64 host
+    arrays; the library computes and copies only those."""
+    if isinstance(which, str):
+        which = (which,)
     bad = set(which) - set(FIELDS)
     if bad:
         raise ValueError(f"unknown fields {sorted(bad)}")

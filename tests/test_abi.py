@@ -194,3 +194,5 @@ def test_size_limits_are_checked_on_host(lib):
 def test_field_selection_is_checked_before_the_library_is_called():
     with pytest.raises(ValueError):
         dsm.dsm_fields(None, 16, 2, which=("C2", "rho"))
+    with pytest.raises(ValueError):
+        dsm.dsm_fields(None, 16, 2, which="rho")

@@ -85,10 +85,11 @@ def test_steps_from_liquid(gpu, dim, kernel):
     assert abs(Fg - Fo) / abs(Fo) < 1e-5
     assert abs(Eg - Eo) <= 1e-3 * abs(Eo) + 1e-12
     # selected fields: the same values, only those returned
-    for which in (("C2",), ("C3",), ("C1", "u"), ("p",)):
+    for which in (("C2",), ("C3",), ("C1", "u"), ("p",), "C2"):
         sel = sim.fields(which)
-        assert set(sel) == set(which)
-        for k in which:
+        names = (which,) if isinstance(which, str) else which
+        assert set(sel) == set(names)
+        for k in names:
             assert np.array_equal(sel[k], fg[k]), k
     # the same FP64 reduction through dsm_diagnostics, with the largest speed
     d = sim.diagnostics()
